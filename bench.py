@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark: split-step grid-point updates/s of the Fourier split-operator hot path.
+
+Workload: 2-D Schroedinger, 2048 x 2048 periodic grid on [-100, 100)^2 a.u.,
+soft-core Coulomb V0 = -1/sqrt(r^2+1) plus the dipole term x.E(t) of a
+sin^2-envelope pulse (E0 = 0.05, omega = 0.057), Gaussian initial state,
+tau = 0.02, 500 steps per run (the field table repeats every 500 steps).
+Seeded synthetic inputs (no dataset), state resident in HBM.
+
+A "step" is one Strang step of the whole grid: the row pass (inverse
+x-transform, merged potential factor, forward x-transform) and the column
+pass (forward y-transform, kinetic factor, inverse y-transform).  `value` is
+the complex64 path (FP32 storage and butterflies, FP64 phases and
+reductions); the complex128 path, fused and in the paper's unfused
+five-launch form, is reported beside it.
+
+Prints ONE JSON line.  --gpus N with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=100)
+    p.add_argument("--n", type=int, default=2048, help="grid points per axis")
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the oracle sample")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--only", choices=["c64", "c128", "all"], default="all")
+    return p.parse_args()
+
+
+def run_steps(g, psi, steps, period):
+    """Propagate `steps` Strang steps, restarting the field table every `period` steps."""
+    done = 0
+    while done < steps:
+        k = min(period, steps - done)
+        g.propagate(psi, 0, k)
+        done += k
+
+
+def bench_path(wl, dtype, flags, steps, warmup):
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype=dtype, flags=flags)
+    g.set_potential(wl.V0)
+    g.set_field(wl.ebar)
+    psi = torch.from_numpy(wl.psi0).to("cuda").to(g.torch_dtype).contiguous()
+    n0 = g.norm(psi)
+    run_steps(g, psi, warmup, wl.nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(g, psi, steps, wl.nsteps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # one more full run from psi0 for the accuracy figures (untimed)
+    psi.copy_(torch.from_numpy(wl.psi0).to("cuda").to(g.torch_dtype))
+    g.propagate(psi, 0, wl.nsteps)
+    drift = g.norm(psi) / n0 - 1
+    final = psi.cpu().numpy()
+    # per-kernel durations: the same launches again with HIP events around each pass
+    g.profile(True)
+    run_steps(g, psi, min(steps, 2 * wl.nsteps), wl.nsteps)
+    kern = {name: g.profile_read(kind) for name, kind in
+            (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
+    g.profile(False)
+    g.close()
+    del psi
+    torch.cuda.empty_cache()
+    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern)
+
+
+def cpu_baseline(wl, budget):
+    """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    cores = oracle.num_threads()
+    psi = wl.psi0.copy()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        psi = oracle.schrodinger(psi, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, wl.ebar, step0=steps, nsteps=1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget or steps >= wl.nsteps:
+            break
+    pts = int(np.prod(wl.n))
+    return dict(value=pts * steps / el, unit="grid-point updates/s", cores=cores, kind="oracle",
+                sample="%d of %d steps of the same %dx%d workload, FP64 radix-2, OpenMP over lines, %.1f s"
+                       % (steps, wl.nsteps, wl.n[0], wl.n[1], el))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (got --gpus %d); multi-GPU sharding is not part of this build"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1012_3911_amd import sfo, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = W.softcore_2d_laser(n=args.n)
+    npts = wl.n[0] * wl.n[1]
+    res = {}
+    paths = [("c64", 0), ("c128", 0), ("c128_unfused", sfo.UNFUSED)]
+    if args.only != "all":
+        paths = [p for p in paths if p[0] == args.only]
+    for name, flags in paths:
+        dtype = name.split("_")[0]
+        res[name] = bench_path(wl, dtype, flags, args.steps, args.warmup)
+        print("# %-13s %.3f ms/step  %.3e updates/s  norm drift %.2e" % (
+            name, 1e3 * res[name]["seconds"] / args.steps, npts * args.steps / res[name]["seconds"],
+            res[name]["drift"]), file=sys.stderr, flush=True)
+
+    head = "c64" if "c64" in res else list(res)[0]
+    r = res[head]
+    ms = 1e3 * r["seconds"] / args.steps
+    value = npts * args.steps / r["seconds"]
+    bytes_state = npts * (8 if head.startswith("c64") else 16)
+    bytes_v0 = npts * (4 if head.startswith("c64") else 8)
+    # algorithmic bytes per launch: column pass reads and writes the state once;
+    # row pass additionally reads V0
+    alg = {"column": 2 * bytes_state, "row": 2 * bytes_state + bytes_v0}
+    kstats = {}
+    for k, (cnt, tot) in r["kernels"].items():
+        if cnt:
+            avg = tot / cnt
+            kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches=cnt)
+    dom = max(kstats, key=lambda k: kstats[k]["avg_us"] * kstats[k]["launches"])
+    achieved = kstats[dom]["gbs"]
+    err_vs_c128 = None
+    if "c64" in res and "c128" in res:
+        a, b = res["c64"]["final"].astype(np.complex128), res["c128"]["final"]
+        err_vs_c128 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    step_bytes = alg["row"] + alg["column"]
+    out = {
+        "metric": "split-step grid-point updates/s (fwd, fwd+adjoint) at stated err; % HBM BW",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2d_schrodinger_softcore_laser %dx%d c64 fwd" % (wl.n[0], wl.n[1]),
+            "grid": list(wl.n), "box": [wl.xmin[0], wl.xmax[0]], "dt": wl.dt, "steps_per_run": wl.nsteps,
+            "field": "x.E(t), E0=0.05, omega=0.057, sin^2 envelope over the run",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_colpass" if dom == "column" else "k_xpass",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "step_model_gbs": step_bytes / (ms * 1e-3) / 1e9,
+        "step_model_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels": kstats,
+        "accuracy": {"c64_norm_drift_per_run": res.get("c64", {}).get("drift"),
+                     "c64_rel_l2_vs_c128_after_run": err_vs_c128,
+                     "c128_norm_drift_per_run": res.get("c128", {}).get("drift")},
+        "paths": {k: {"ms_per_step": 1e3 * v["seconds"] / args.steps,
+                      "updates_per_s": npts * args.steps / v["seconds"]} for k, v in res.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

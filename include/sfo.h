@@ -1,0 +1,171 @@
+/*
+ * sfo.h - C ABI of the Fourier split-operator library for AMD MI355X (gfx950).
+ *
+ * The library propagates a wave function by the split-operator method of
+ * Bauke & Keitel, "Accelerating the Fourier split operator method via
+ * graphics processing units":  each step is the Strang factorisation
+ *
+ *     w(t+tau) = U_A1(1/2) F^-1 { U~_A2(1) F { U_A1(1/2) w(t) } }
+ *
+ * (Sec. 2.1, eqs. U_split and step_t_to_t+dt_F), with
+ *   - Schroedinger (Sec. 2.2, dipole approximation in the length gauge):
+ *     U_A1(1/2) = exp(-i [tau V0(x) + x.Ebar_n] / (2 hbar)),
+ *     U~_A2(1)  = exp(-i hbar tau |k|^2 / (2 m));
+ *   - Dirac, d = 2, 4-spinor in the Dirac representation (Sec. 2.3):
+ *     U_A1(1/2) = exp(-i tau V0/(2 hbar)) [cos a + i sin a alpha_2],
+ *                 a = q c Abar_y(x)/(2 hbar)              (eq. exp_alpha),
+ *     U~_A2(1)  = cos(E tau/hbar) - i sin(E tau/hbar) H(hbar k)/E,
+ *                 H = c alpha.p + m c^2 beta, E = sqrt(m^2c^4 + c^2 p^2)
+ *                 (eq. U_A_2_DE, closed form of its diagonalisation).
+ * Ebar_n = Int_{t_n}^{t_n+tau} E(t') dt' and Abar_n = Int A_y dt' are step
+ * integrals supplied by the caller; both half steps of step n use the same
+ * integral (eq. U_split).  The DFT is unnormalised forward,
+ * exp(-2 pi i j m/N), with 1/N on the inverse; k_m = 2 pi m / L for
+ * m in [-N/2, N/2) in FFT order (the Nyquist mode is negative).
+ *
+ * Conventions shared by every entry point
+ *   - Units are the caller's; atomic units give hbar = m = 1, q = -1.
+ *   - A state is a contiguous device array, layout [comp][z][y][x] with x
+ *     fastest (n[0] is the x size), complex64 (interleaved float re, im)
+ *     or complex128 (interleaved double re, im) per desc.dtype; comp = 4
+ *     for Dirac, 1 otherwise.  The caller owns every state buffer.
+ *   - x_j = xmin + j dx, dx = (xmax - xmin)/n: the box is periodic and the
+ *     right end is excluded.
+ *   - All work is enqueued on the stream given at creation and is
+ *     asynchronous, except sfo_norm and sfo_overlap, which return values
+ *     to the host and therefore synchronise that stream.
+ *   - Every function returns an sfo_status; on failure nothing has been
+ *     enqueued and sfo_last_error() describes the reason.  No exception
+ *     crosses the ABI.  A grid handle is not thread-safe.
+ */
+#ifndef SFO_H
+#define SFO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfo_grid_s *sfo_grid;
+
+typedef enum {
+    SFO_OK = 0,
+    SFO_E_INVALID = -1,     /* bad argument: null pointer, size, index, table too short */
+    SFO_E_UNSUPPORTED = -2, /* valid request this build does not implement */
+    SFO_E_NOMEM = -3,       /* device allocation failed */
+    SFO_E_HIP = -4,         /* HIP runtime error (no device, launch failure) */
+    SFO_E_STATE = -5        /* call out of order (e.g. no potential set) */
+} sfo_status;
+
+enum { SFO_SCHRODINGER = 0, SFO_DIRAC = 1 };
+enum { SFO_C64 = 0, SFO_C128 = 1 };
+
+/* flags */
+enum {
+    SFO_V0_FP64 = 1u << 0, /* keep V0 in FP64 also for complex64 states (default: FP32) */
+    SFO_UNFUSED = 1u << 1  /* run the paper's five-launch step (phase kernel, FFT, kinetic
+                              kernel, inverse FFT, phase kernel) instead of the fused passes;
+                              a reference configuration of the same kernels */
+};
+
+typedef struct {
+    int32_t ndim;      /* 1, 2 or 3 (Dirac: 2) */
+    int64_t n[3];      /* points per axis, x first; powers of two, 1-D 64..8192, 2-D/3-D 64..4096 */
+    double xmin[3];    /* box per axis, x first */
+    double xmax[3];
+    int32_t equation;  /* SFO_SCHRODINGER or SFO_DIRAC */
+    int32_t dtype;     /* SFO_C64 or SFO_C128 */
+    double dt;         /* tau */
+    double mass;       /* m (a.u.: 1) */
+    double charge;     /* q (a.u. electron: -1); used by the Dirac vector-potential factor */
+    double c;          /* speed of light (a.u.: 137.036); Dirac only */
+    double hbar;       /* (a.u.: 1) */
+    uint32_t flags;
+} sfo_grid_desc;
+
+/* Create a grid handle: validates desc, allocates the library's device
+ * tables (twiddles, kinetic factors, V0 storage, reduction scratch) on the
+ * current HIP device, and binds the handle to `hip_stream` (a hipStream_t,
+ * NULL = default stream).  V0 starts at zero and the field tables empty.
+ * Errors: SFO_E_INVALID (desc), SFO_E_UNSUPPORTED (size or equation/ndim
+ * combination), SFO_E_HIP (no device), SFO_E_NOMEM. */
+sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid *out);
+
+/* Release every library-owned buffer of the handle (waits for its stream). */
+sfo_status sfo_destroy_grid(sfo_grid g);
+
+/* Copy the static potential energy V0(x) (FP64, N_points values, device
+ * pointer, layout [z][y][x]) into the handle, which keeps it in FP32 for
+ * complex64 states unless SFO_V0_FP64 is set, in FP64 otherwise.  The
+ * caller's buffer may be freed after the stream reaches this call. */
+sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev);
+
+/* Copy the per-step field integrals Ebar[step][axis] (host, FP64,
+ * nsteps x ndim, axis x first) into a device table indexed by absolute step
+ * number.  Steps beyond the table are an error at propagation time; with no
+ * table the field is zero.  Schroedinger only. */
+sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
+
+/* Copy the per-step vector-potential integrals Abar_y[step][ix] (host,
+ * FP64, nsteps x n[0]) of a field A = A_y(x, t) y_hat.  Dirac only. */
+sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps);
+
+/* One un-merged Strang step number `step_index` applied in place to psi. */
+sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index);
+
+/* Steps step0 .. step0+nsteps-1 in place.  Consecutive half steps of the
+ * potential are merged into one factor (exact up to rounding); the result
+ * equals nsteps calls of sfo_step to rounding. */
+sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nsteps);
+
+/* Reverse-mode gradient through sfo_propagate(g, psi0, step0, nsteps)
+ * (Schroedinger only).  On entry psi holds psi(T) = the forward result and
+ * g_vec holds 2 dL/dconj(psi(T)) (the complex-autograd convention) for a
+ * real loss L.  The states are walked back with the exact inverse step (no
+ * stored trajectory); on return psi holds the recomputed psi(0) and g_vec
+ * holds 2 dL/dconj(psi(0)).  dL_debar_dev (device, FP64, nsteps x ndim,
+ * row s for step step0+s) receives dL/dEbar; dL_dV0_dev (device, FP64,
+ * N_points, may be NULL) receives dL/dV0.  Both are overwritten. */
+sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
+                       double *dL_debar_dev, double *dL_dV0_dev);
+
+/* ||psi||^2 = dV sum |psi|^2 over all points and components, accumulated in
+ * FP64; written to *out_host.  Synchronises the stream. */
+sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host);
+
+/* <a|b> = dV sum conj(a) b in FP64; out_host[0] = real, out_host[1] = imaginary.
+ * Synchronises the stream. */
+sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double *out_host);
+
+/* Unnormalised n-dimensional DFT of every component of psi in place,
+ * exp(sign 2 pi i j m / N) along each axis, sign = -1 or +1 (the transform
+ * the step uses internally; exposed for diagnostics). */
+sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign);
+
+/* Kernel timing (diagnostics).  While enabled, every pass the handle launches
+ * is bracketed by a pair of HIP events recorded on the handle's stream;
+ * enabling clears what was collected.  sfo_profile_read synchronises the
+ * stream and returns, for one kernel kind, the number of launches and their
+ * summed duration in milliseconds. */
+enum {
+    SFO_KERNEL_ROW = 0,    /* contiguous x-axis pass (transform, potential factor) */
+    SFO_KERNEL_COLUMN = 1, /* strided y-axis pass (2-D: transform, kinetic factor) */
+    SFO_KERNEL_ZCOLUMN = 2,/* strided z-axis pass (3-D: transform, kinetic factor) */
+    SFO_KERNEL_LINE1D = 3, /* whole-run 1-D kernel */
+    SFO_KERNEL_KINDS = 4
+};
+sfo_status sfo_profile_enable(sfo_grid g, int32_t on);
+sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *total_ms);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *sfo_last_error(void);
+
+/* Library version string. */
+const char *sfo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFO_H */

@@ -1,0 +1,310 @@
+// In-workgroup Stockham FFT engine for gfx950 (wave64, LDS exchange).
+//
+// A line of N complex values is spread over T = N/RV threads, each holding
+// RV values in registers in CYCLIC order: thread t owns x[t + m*T],
+// m = 0..RV-1.  The transform is a sequence of Stockham autosort stages
+// (radix r, span L = product of the earlier radices):
+//     butterfly b in [0, N/r):  k = b mod L,  j0 = b / L
+//     inputs  x[b + j N/r], j < r, the j-th scaled by W_{L r}^{j k}
+//     r-point DFT, output m to position j0 L r + k + m L.
+// With the cyclic layout every stage reads its butterfly inputs from the
+// thread's own registers, and the LAST stage (L r = N, so j0 = 0) writes its
+// outputs back into the same cyclic layout.  Only intermediate stages go
+// through LDS, so a forward transform, a point-wise factor and an inverse
+// transform chain with no exchange between them.
+//
+// Precision.  Twiddles come from FP64 tables.  For complex64 each twiddle is
+// stored as an FP32 hi/lo pair and applied with FMAs, and the internal
+// constants of the radix-8/16 codelets likewise, so that the rounded
+// twiddle's modulus error (about 3e-8 for angles near 45 degrees, the same
+// for every step) does not turn into a systematic norm drift; what remains
+// is the rounding of each arithmetic result, which is not systematic.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfo {
+
+template <typename R>
+struct __align__(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+// Twiddle table entry: FP32 hi/lo pair for complex64, plain FP64 for complex128.
+template <typename R> struct TwEntry;
+template <> struct __align__(16) TwEntry<float> { float hr, hi, lr, li; };
+template <> struct __align__(16) TwEntry<double> { double r, i; };
+
+template <typename R> __device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+
+// a * exp(DIR * i pi/2): DIR = -1 gives -i a, DIR = +1 gives i a (exact).
+template <int DIR, typename R> __device__ __forceinline__ cx<R> mul_quarter(cx<R> a)
+{
+    if (DIR < 0) return {a.im, -a.re};
+    return {-a.im, a.re};
+}
+
+// a * (wr + i wi) with the twiddle given as an FP32 hi/lo pair.  The small
+// products with the lo parts are summed FIRST and each later FMA rounds the
+// complete partial value, so the lo parts are not absorbed: adding them to an
+// already rounded product would drop them below half an ulp and leave the
+// rounded twiddle's modulus error in place, a norm loss of a few 1e-8 per
+// multiply that repeats identically every step.
+__device__ __forceinline__ cx<float> cmul_hl(cx<float> a, float hr, float hi, float lr, float li)
+{
+    float re = __builtin_fmaf(a.re, lr, -(a.im * li));
+    re = __builtin_fmaf(-a.im, hi, re);
+    re = __builtin_fmaf(a.re, hr, re);
+    float im = __builtin_fmaf(a.re, li, a.im * lr);
+    im = __builtin_fmaf(a.im, hr, im);
+    im = __builtin_fmaf(a.re, hi, im);
+    return {re, im};
+}
+
+__device__ __forceinline__ cx<double> cmul_d(cx<double> a, double wr, double wi)
+{
+    return {__builtin_fma(a.re, wr, -(a.im * wi)), __builtin_fma(a.re, wi, a.im * wr)};
+}
+
+// Table twiddle W_N^idx (forward table), conjugated for the inverse transform.
+template <int DIR> __device__ __forceinline__ cx<float> twiddle(cx<float> a, const TwEntry<float> *tw, int idx)
+{
+    TwEntry<float> w = tw[idx];
+    if (DIR > 0) { w.hi = -w.hi; w.li = -w.li; }
+    return cmul_hl(a, w.hr, w.hi, w.lr, w.li);
+}
+template <int DIR> __device__ __forceinline__ cx<double> twiddle(cx<double> a, const TwEntry<double> *tw, int idx)
+{
+    TwEntry<double> w = tw[idx];
+    return cmul_d(a, w.r, DIR > 0 ? -w.i : w.i);
+}
+
+// cos(2 pi k / 16), k = 0..15 (FP64 constants of the radix-8/16 codelets).
+__host__ __device__ constexpr double cos16(int k)
+{
+    constexpr double c[16] = {1.0,
+                              0.92387953251128675613,
+                              0.70710678118654752440,
+                              0.38268343236508977173,
+                              0.0,
+                              -0.38268343236508977173,
+                              -0.70710678118654752440,
+                              -0.92387953251128675613,
+                              -1.0,
+                              -0.92387953251128675613,
+                              -0.70710678118654752440,
+                              -0.38268343236508977173,
+                              0.0,
+                              0.38268343236508977173,
+                              0.70710678118654752440,
+                              0.92387953251128675613};
+    return c[k & 15];
+}
+__host__ __device__ constexpr double sin16(int k) { return cos16((k + 12) & 15); }
+
+// a * W_NR^E for the codelet constants, W = exp(DIR 2 pi i / NR), NR | 16.
+template <int DIR, int NR, int E, typename R> __device__ __forceinline__ cx<R> cmul_const(cx<R> a)
+{
+    constexpr int e16 = ((E * (16 / NR)) % 16 + 16) % 16;
+    if constexpr (e16 == 0) {
+        return a;
+    } else if constexpr (e16 == 8) {
+        return {-a.re, -a.im};
+    } else if constexpr (e16 == 4) {
+        return mul_quarter<DIR>(a);
+    } else if constexpr (e16 == 12) {
+        return mul_quarter<-DIR>(a);
+    } else {
+        constexpr double wr = cos16(e16);
+        constexpr double wi = (DIR < 0 ? -1.0 : 1.0) * sin16(e16);
+        if constexpr (sizeof(R) == 4) {
+            constexpr float hr = (float)wr, hi = (float)wi;
+            constexpr float lr = (float)(wr - (double)hr), li = (float)(wi - (double)hi);
+            return cmul_hl(a, hr, hi, lr, li);
+        } else {
+            return cmul_d(a, wr, wi);
+        }
+    }
+}
+
+template <int NR, int DIR, int N1, int N2, int J2 = 0, int M1 = 0, typename R>
+__device__ __forceinline__ void twiddle_grid(cx<R> (&a)[N2][N1])
+{
+    if constexpr (J2 < N2) {
+        if constexpr (M1 < N1) {
+            a[J2][M1] = cmul_const<DIR, NR, J2 * M1>(a[J2][M1]);
+            twiddle_grid<NR, DIR, N1, N2, J2, M1 + 1>(a);
+        } else {
+            twiddle_grid<NR, DIR, N1, N2, J2 + 1, 0>(a);
+        }
+    }
+}
+
+// In-register DFT of size NR (1, 2, 4, 8, 16), natural order in and out:
+// y_m = sum_j v_j exp(DIR 2 pi i j m / NR).  Sizes above 4 split as 4 x NR/4.
+template <int NR, int DIR, typename R> __device__ __forceinline__ void dft(cx<R> *v)
+{
+    if constexpr (NR == 1) {
+        return;
+    } else if constexpr (NR == 2) {
+        cx<R> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (NR == 4) {
+        cx<R> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        cx<R> s13 = cadd(v[1], v[3]), d13 = mul_quarter<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else {
+        constexpr int N1 = 4, N2 = NR / 4;
+        cx<R> a[N2][N1];
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) {
+#pragma unroll
+            for (int j1 = 0; j1 < N1; ++j1) a[j2][j1] = v[N2 * j1 + j2];
+            dft<N1, DIR>(a[j2]);
+        }
+        // twiddles W_NR^{j2 m1}
+        twiddle_grid<NR, DIR, N1, N2>(a);
+#pragma unroll
+        for (int m1 = 0; m1 < N1; ++m1) {
+            cx<R> b[N2];
+#pragma unroll
+            for (int j2 = 0; j2 < N2; ++j2) b[j2] = a[j2][m1];
+            dft<N2, DIR>(b);
+#pragma unroll
+            for (int m2 = 0; m2 < N2; ++m2) v[m1 + N1 * m2] = b[m2];
+        }
+    }
+}
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// LDS slot of logical element p of a line (one pad slot every 16 elements).
+__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
+__host__ __device__ constexpr int lds_line_stride(int N) { return N + N / 16 + 1; }
+
+// Shape of an N-point line transform with RAD values per thread.
+template <int N, int RAD> struct LineShape {
+    static constexpr int RV = N < RAD ? N : RAD;         // values per thread
+    static constexpr int T = N / RV;                     // threads per line
+    static constexpr int LOGR = ilog2(RV);
+    static constexpr int NFULL = LOGR ? ilog2(N) / LOGR : 0;
+    static constexpr int REM = N >> (NFULL * LOGR);      // leading small radix, 1 if none
+    static constexpr int NST = NFULL + (REM > 1 ? 1 : 0);
+    static constexpr int radix(int s) { return (REM > 1 && s == 0) ? REM : RV; }
+    static constexpr int span(int s) { return s == 0 ? 1 : span(s - 1) * radix(s - 1); }
+    static constexpr int LDS = lds_line_stride(N);       // complex slots per line in LDS
+};
+
+// One Stockham stage S of an N-point transform (see the file comment).
+// v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in line.
+template <typename R, int N, int RAD, int DIR, int S, int NV>
+__device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
+{
+    using Sh = LineShape<N, RAD>;
+    static_assert(NV == Sh::RV, "register array size must match the line shape");
+    // keep the scheduler from pulling the next stage's table loads (and their
+    // registers) ahead into this one
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int RV = Sh::RV, T = Sh::T;
+    constexpr int r = Sh::radix(S), L = Sh::span(S), NB = RV / r;
+    constexpr bool last = (S == Sh::NST - 1);
+    constexpr int TWS = N / (L * r);  // table stride of W_{L r}
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        cx<R> u[r];
+#pragma unroll
+        for (int j = 0; j < r; ++j) u[j] = v[i + j * NB];
+        const int b = t + i * T;
+        const int k = b & (L - 1);
+        if constexpr (L > 1) {
+#pragma unroll
+            for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, j * k * TWS);
+        }
+        dft<r, DIR>(u);
+        if constexpr (last) {
+#pragma unroll
+            for (int m = 0; m < r; ++m) v[i + m * NB] = u[m];
+        } else {
+            const int base = (b / L) * (L * r) + k;
+#pragma unroll
+            for (int m = 0; m < r; ++m) sh[lds_pad(base + m * L)] = u[m];
+        }
+    }
+    if constexpr (!last) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < RV; ++m) v[m] = sh[lds_pad(t + m * T)];
+        __syncthreads();
+    }
+}
+
+template <typename R, int N, int RAD, int DIR, int S = 0, int NV>
+__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
+{
+    if constexpr (S < LineShape<N, RAD>::NST) {
+        fft_stage<R, N, RAD, DIR, S>(v, sh, t, tw);
+        fft_line<R, N, RAD, DIR, S + 1>(v, sh, t, tw);
+    }
+}
+
+// ---------------------------------------------------------------- phases --
+// exp(-i theta) with theta in FP64.  Range reduction by quadrant with a
+// two-term (Cody-Waite) pi/2 and one FMA, then the Taylor series of sin and
+// cos on [-pi/4, pi/4] to degree 15/16 (truncation below 5e-17), then the
+// quadrant's swap and signs.  Accurate to a few ulp of FP64 for
+// |theta| < 1e6, far beyond the phases of a step.
+__device__ __forceinline__ void sincos_fp64(double x, double &s, double &c)
+{
+    const double two_over_pi = 0.63661977236758134308;
+    const double pio2_hi = 1.5707963267948966192;     // pi/2 rounded to FP64
+    const double pio2_lo = 6.1232339957367658e-17;    // pi/2 - pio2_hi
+    const double q = rint(x * two_over_pi);
+    const double r = __builtin_fma(-q, pio2_lo, __builtin_fma(-q, pio2_hi, x));
+    const double r2 = r * r;
+    double ps = -7.6471637318198164759e-13;           // -1/15!
+    ps = __builtin_fma(ps, r2, 1.6059043836821614599e-10);  // 1/13!
+    ps = __builtin_fma(ps, r2, -2.5052108385441718775e-08); // -1/11!
+    ps = __builtin_fma(ps, r2, 2.7557319223985890653e-06);  // 1/9!
+    ps = __builtin_fma(ps, r2, -1.9841269841269841270e-04); // -1/7!
+    ps = __builtin_fma(ps, r2, 8.3333333333333333333e-03);  // 1/5!
+    ps = __builtin_fma(ps, r2, -1.6666666666666666667e-01); // -1/3!
+    const double sr = __builtin_fma(ps * r2, r, r);
+    double pc = 4.7794773323873852974e-14;            // 1/16!
+    pc = __builtin_fma(pc, r2, -1.1470745597729724714e-11); // -1/14!
+    pc = __builtin_fma(pc, r2, 2.0876756987868098979e-09);  // 1/12!
+    pc = __builtin_fma(pc, r2, -2.7557319223985890653e-07); // -1/10!
+    pc = __builtin_fma(pc, r2, 2.4801587301587301587e-05);  // 1/8!
+    pc = __builtin_fma(pc, r2, -1.3888888888888888889e-03); // -1/6!
+    pc = __builtin_fma(pc, r2, 4.1666666666666666667e-02);  // 1/4!
+    pc = __builtin_fma(pc, r2, -0.5);
+    const double cr = __builtin_fma(pc, r2, 1.0);
+    // quadrant q mod 4 without branches: odd quadrants swap sin and cos,
+    // quadrants 2 and 3 negate sin, quadrants 1 and 2 negate cos
+    const int quad = (int)q & 3;
+    const double ss = (quad & 1) ? cr : sr;
+    const double cc = (quad & 1) ? sr : cr;
+    s = (quad & 2) ? -ss : ss;
+    c = ((quad + 1) & 2) ? -cc : cc;
+}
+
+template <typename R> __device__ __forceinline__ cx<R> mul_phase(cx<R> v, double c, double s)
+{
+    // v * (c + i s) in FP64, rounded once
+    double re = (double)v.re * c - (double)v.im * s;
+    double im = (double)v.re * s + (double)v.im * c;
+    return {(R)re, (R)im};
+}
+
+template <typename R> __device__ __forceinline__ cx<R> mul_expmi(cx<R> v, double th)
+{
+    double s, c;
+    sincos_fp64(th, s, c);
+    return mul_phase(v, c, -s);
+}
+
+}  // namespace sfo

@@ -1,0 +1,574 @@
+// C ABI layer: validation, library-owned device tables, and the pass
+// sequences of a split-operator run.  See include/sfo.h for the contract.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sfo.h"
+#include "sfo_impl.h"
+
+using namespace sfo;
+
+namespace {
+
+thread_local std::string g_err;
+
+sfo_status fail(sfo_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+sfo_status fail(sfo_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? SFO_E_NOMEM : SFO_E_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+bool is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+struct sfo_grid_s {
+    sfo_grid_desc d{};
+    hipStream_t st = nullptr;
+    int ndim = 1;
+    int ncomp = 1;
+    int64_t n[3] = {1, 1, 1};
+    int64_t ntot = 1;
+    double dx[3] = {0, 0, 0};
+    double dv = 1;
+    bool c128 = false;
+    bool v0_fp64 = false;
+    void *V0 = nullptr;
+    std::vector<double> ebar;  // host copy, nsteps x ndim
+    double *ebar_d = nullptr;  // device copy (1-D kernel reads it)
+    int64_t ebar_steps = 0;
+    std::vector<double> abar;  // Dirac: nsteps x n[0]
+    double *abar_d = nullptr;
+    int64_t abar_steps = 0;
+    void *tw[3] = {nullptr, nullptr, nullptr};     // per-axis twiddle tables
+    double2 *kin[3] = {nullptr, nullptr, nullptr}; // per-axis kinetic factors (1/Ntot in axis 0)
+    double *kvec[3] = {nullptr, nullptr, nullptr}; // per-axis wave numbers (Dirac)
+    double2 *one = nullptr;                        // {1, 0}
+    double *red = nullptr;                         // reduction partials + result
+    // kernel timing: event pairs per kernel kind while profiling is on
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
+    std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+void prof_clear(sfo_grid g)
+{
+    for (auto &v : g->ev) {
+        for (auto &p : v) {
+            g->ev_pool.push_back(p.first);
+            g->ev_pool.push_back(p.second);
+        }
+        v.clear();
+    }
+}
+
+void free_grid(sfo_grid g)
+{
+    if (!g) return;
+    prof_clear(g);
+    for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    (void)hipFree(g->V0);
+    (void)hipFree(g->ebar_d);
+    (void)hipFree(g->abar_d);
+    for (int a = 0; a < 3; ++a) {
+        (void)hipFree(g->tw[a]);
+        (void)hipFree(g->kin[a]);
+        (void)hipFree(g->kvec[a]);
+    }
+    (void)hipFree(g->one);
+    (void)hipFree(g->red);
+    delete g;
+}
+
+// Wave number of FFT index j on an axis of n points and length L (Nyquist negative).
+double wavenumber(int64_t j, int64_t n, double L)
+{
+    const int64_t m = j < n / 2 ? j : j - n;
+    return 2.0 * M_PI * (double)m / L;
+}
+
+// exp(-2 pi i j / n) for j < n, from an angle reduced to the first octant so
+// that symmetric entries are exact mirrors of each other.
+void unit_root(int64_t j, int64_t n, double &c, double &s)
+{
+    // angle = 2 pi j / n; work with j/n in eighths
+    const int64_t n8 = n >= 8 ? n / 8 : 0;
+    if (n8 == 0) {
+        const double a = 2.0 * M_PI * (double)j / (double)n;
+        c = std::cos(a);
+        s = -std::sin(a);
+        if (std::fabs(c) < 1e-17) c = 0.0;
+        if (std::fabs(s) < 1e-17) s = 0.0;
+        return;
+    }
+    const int64_t oct = j / n8, r = j % n8;
+    // base angle within the octant, mirrored for odd octants
+    const bool mirror = (oct & 1) != 0;
+    const int64_t rr = mirror ? n8 - r : r;
+    const double a = 2.0 * M_PI * (double)rr / (double)n;  // in [0, pi/4]
+    double cb = std::cos(a), sb = std::sin(a);
+    if (rr == n8) cb = sb = std::sqrt(0.5);
+    // point on the unit circle at angle oct*pi/4 +- a (cos, sin)
+    double cc, ss;
+    switch (oct & 7) {
+    case 0: cc = cb; ss = sb; break;
+    case 1: cc = sb; ss = cb; break;
+    case 2: cc = -sb; ss = cb; break;
+    case 3: cc = -cb; ss = sb; break;
+    case 4: cc = -cb; ss = -sb; break;
+    case 5: cc = -sb; ss = -cb; break;
+    case 6: cc = sb; ss = -cb; break;
+    default: cc = cb; ss = -sb; break;
+    }
+    c = cc;
+    s = -ss;  // forward root: exp(-i angle)
+}
+
+sfo_status make_twiddles(sfo_grid g, int a)
+{
+    const int64_t n = g->n[a];
+    if (g->c128) {
+        std::vector<TwEntry<double>> h(n);
+        for (int64_t j = 0; j < n; ++j) unit_root(j, n, h[j].r, h[j].i);
+        HIP_TRY(hipMalloc(&g->tw[a], sizeof(TwEntry<double>) * n));
+        HIP_TRY(hipMemcpy(g->tw[a], h.data(), sizeof(TwEntry<double>) * n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<TwEntry<float>> h(n);
+        for (int64_t j = 0; j < n; ++j) {
+            double c, s;
+            unit_root(j, n, c, s);
+            h[j].hr = (float)c;
+            h[j].hi = (float)s;
+            h[j].lr = (float)(c - (double)h[j].hr);
+            h[j].li = (float)(s - (double)h[j].hi);
+        }
+        HIP_TRY(hipMalloc(&g->tw[a], sizeof(TwEntry<float>) * n));
+        HIP_TRY(hipMemcpy(g->tw[a], h.data(), sizeof(TwEntry<float>) * n, hipMemcpyHostToDevice));
+    }
+    return SFO_OK;
+}
+
+// exp(-i hbar tau k^2 / (2 m)) per axis; axis 0 also carries 1/Ntot (a power of two: exact).
+sfo_status make_kinetic(sfo_grid g, int a)
+{
+    const int64_t n = g->n[a];
+    const double L = g->d.xmax[a] - g->d.xmin[a];
+    std::vector<double2> h(n);
+    std::vector<double> kv(n);
+    const double scale = a == 0 ? 1.0 / (double)g->ntot : 1.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double k = wavenumber(j, n, L);
+        kv[j] = k;
+        const double ph = g->d.hbar * g->d.dt * k * k / (2.0 * g->d.mass);
+        h[j].x = std::cos(ph) * scale;
+        h[j].y = -std::sin(ph) * scale;
+    }
+    HIP_TRY(hipMalloc(&g->kin[a], sizeof(double2) * n));
+    HIP_TRY(hipMemcpy(g->kin[a], h.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&g->kvec[a], sizeof(double) * n));
+    HIP_TRY(hipMemcpy(g->kvec[a], kv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    return SFO_OK;
+}
+
+hipEvent_t prof_event(sfo_grid g)
+{
+    if (!g->ev_pool.empty()) {
+        hipEvent_t e = g->ev_pool.back();
+        g->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` bracketed by events of kind `kind` when profiling is on.
+template <typename F> hipError_t timed(sfo_grid g, int kind, F &&fn)
+{
+    if (!g->prof) return fn();
+    hipEvent_t a = prof_event(g), b = prof_event(g);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, g->st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, g->st);
+    if (e == hipSuccess) g->ev[kind].push_back({a, b});
+    return e;
+}
+
+// Field integral of step s along axis a (zero without a table).
+double ebar_at(const sfo_grid g, int64_t s, int a)
+{
+    if (g->ebar_steps == 0) return 0.0;
+    return g->ebar[(size_t)(s * g->ndim + a)];
+}
+
+// Real-space factor covering the second half of step `sa` and the first half
+// of step `sb` (either may be -1 for "none"); sgn = -1 conjugates.
+PhaseArgs phase_args(const sfo_grid g, int64_t sa, int64_t sb, int sgn)
+{
+    PhaseArgs p{};
+    const double inv2h = 1.0 / (2.0 * g->d.hbar);
+    const int halves = (sa >= 0) + (sb >= 0);
+    p.aV = g->d.dt * inv2h * halves;
+    for (int a = 0; a < 3; ++a) {
+        double e = 0.0;
+        if (a < g->ndim) {
+            if (sa >= 0) e += ebar_at(g, sa, a);
+            if (sb >= 0) e += ebar_at(g, sb, a);
+        }
+        p.e[a] = e * inv2h;
+        p.xmin[a] = a < g->ndim ? g->d.xmin[a] : 0.0;
+        p.dx[a] = a < g->ndim ? g->dx[a] : 0.0;
+    }
+    p.sgn = sgn;
+    return p;
+}
+
+template <typename R> sfo_status schro_xpass(sfo_grid g, void *psi, int64_t sa, int64_t sb, int sgn, int mode)
+{
+    const PhaseArgs ph = phase_args(g, sa, sb, sgn);
+    HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
+        return launch_xpass<R>((int)g->n[0], (cx<R> *)psi, g->n[1] * g->n[2], (int)g->n[1], g->V0, g->v0_fp64,
+                               g->tw[0], ph, mode, g->st);
+    }));
+    return SFO_OK;
+}
+
+// Forward/inverse transforms and the kinetic factor along the non-x axes.
+// mode: M_FWD, M_INV, M_KIN combinations (in the order FWD, KIN, INV).
+template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, int mode, int sgn)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    if (g->ndim == 2) {
+        KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
+        HIP_TRY(timed(g, SFO_KERNEL_COLUMN,
+                      [&] { return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, 1, 0, g->tw[1], k, mode, g->st); }));
+    } else {
+        // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
+        KinArgs none{g->one, g->one, g->one, 1, 1};
+        KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
+        if (mode & M_FWD)
+            HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
+                return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, g->tw[1], none, M_FWD, g->st);
+            }));
+        HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
+            return launch_colpass<R>((int)nz, (cx<R> *)psi, nx * ny, nx * ny, 1, 0, g->tw[2], k, mode, g->st);
+        }));
+        if (mode & M_INV)
+            HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
+                return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, g->tw[1], none, M_INV, g->st);
+            }));
+    }
+    return SFO_OK;
+}
+
+sfo_status check_steps(const sfo_grid g, int64_t step0, int64_t nsteps)
+{
+    if (step0 < 0 || nsteps < 0) return fail(SFO_E_INVALID, "negative step index or count");
+    if (g->ebar_steps > 0 && step0 + nsteps > g->ebar_steps)
+        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the field table (%lld steps)", (long long)step0,
+                    (long long)(step0 + nsteps - 1), (long long)g->ebar_steps);
+    if (g->d.equation == SFO_DIRAC && g->abar_steps > 0 && step0 + nsteps > g->abar_steps)
+        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the vector-potential table (%lld steps)",
+                    (long long)step0, (long long)(step0 + nsteps - 1), (long long)g->abar_steps);
+    return SFO_OK;
+}
+
+// Schroedinger run of nsteps, forward (dir = +1) or inverse (dir = -1, last step first).
+template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0, int64_t nsteps, int dir)
+{
+    if (nsteps == 0) return SFO_OK;
+    auto step_of = [&](int64_t s) { return dir > 0 ? step0 + s : step0 + nsteps - 1 - s; };
+    if (g->ndim == 1) {
+        Run1DArgs a{};
+        a.kin = g->kin[0];
+        a.ebar = g->ebar_steps ? g->ebar_d : nullptr;
+        a.step0 = step0;
+        a.nsteps = nsteps;
+        a.aV_half = g->d.dt / (2.0 * g->d.hbar);
+        a.inv_2hbar = 1.0 / (2.0 * g->d.hbar);
+        a.xmin = g->d.xmin[0];
+        a.dx = g->dx[0];
+        a.dir = dir;
+        HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
+            return launch_1d<R>((int)g->n[0], (cx<R> *)psi, 1, g->ntot, g->V0, g->v0_fp64, g->tw[0], a, g->st);
+        }));
+        return SFO_OK;
+    }
+    sfo_status s;
+    if (g->d.flags & SFO_UNFUSED) {
+        // the paper's sequence: phase kernel, FFT, kinetic kernel, inverse FFT, phase kernel
+        for (int64_t j = 0; j < nsteps; ++j) {
+            const int64_t st = step_of(j);
+            if ((s = schro_xpass<R>(g, psi, -1, st, dir, M_PHASE))) return s;
+            if ((s = schro_xpass<R>(g, psi, -1, -1, dir, M_FWD))) return s;
+            if ((s = schro_colpasses<R>(g, psi, M_FWD, dir))) return s;
+            if ((s = schro_colpasses<R>(g, psi, M_KIN, dir))) return s;
+            if ((s = schro_colpasses<R>(g, psi, M_INV, dir))) return s;
+            if ((s = schro_xpass<R>(g, psi, -1, -1, dir, M_INV))) return s;
+            if ((s = schro_xpass<R>(g, psi, st, -1, dir, M_PHASE))) return s;
+        }
+        return SFO_OK;
+    }
+    if ((s = schro_xpass<R>(g, psi, -1, step_of(0), dir, M_PHASE | M_FWD))) return s;
+    for (int64_t j = 0; j < nsteps; ++j) {
+        if ((s = schro_colpasses<R>(g, psi, M_FWD | M_KIN | M_INV, dir))) return s;
+        const bool more = j + 1 < nsteps;
+        if ((s = schro_xpass<R>(g, psi, step_of(j), more ? step_of(j + 1) : -1, dir,
+                                M_INV | M_PHASE | (more ? M_FWD : 0))))
+            return s;
+    }
+    return SFO_OK;
+}
+
+template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
+{
+    const int mode = sign < 0 ? M_FWD : M_INV;
+    for (int c = 0; c < g->ncomp; ++c) {
+        cx<R> *p = (cx<R> *)psi + c * g->ntot;
+        PhaseArgs ph{};
+        ph.sgn = 1;
+        HIP_TRY(launch_xpass<R>((int)g->n[0], p, g->n[1] * g->n[2], (int)g->n[1], g->V0, g->v0_fp64, g->tw[0], ph,
+                                mode, g->st));
+        if (g->ndim >= 2) {
+            const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+            KinArgs none{g->one, g->one, g->one, 1, 1};
+            HIP_TRY(launch_colpass<R>((int)ny, p, nx, nx, (int)nz, nx * ny, g->tw[1], none, mode, g->st));
+            if (g->ndim == 3)
+                HIP_TRY(launch_colpass<R>((int)nz, p, nx * ny, nx * ny, 1, 0, g->tw[2], none, mode, g->st));
+        }
+    }
+    return SFO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sfo_last_error(void) { return g_err.c_str(); }
+
+const char *sfo_version(void) { return "sfo 0.1 (gfx950)"; }
+
+sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid *out)
+{
+    g_err.clear();
+    if (!desc || !out) return fail(SFO_E_INVALID, "null descriptor or output handle");
+    *out = nullptr;
+    const sfo_grid_desc &d = *desc;
+    if (d.ndim < 1 || d.ndim > 3) return fail(SFO_E_INVALID, "ndim must be 1, 2 or 3 (got %d)", d.ndim);
+    if (d.equation != SFO_SCHRODINGER && d.equation != SFO_DIRAC)
+        return fail(SFO_E_INVALID, "unknown equation %d", d.equation);
+    if (d.dtype != SFO_C64 && d.dtype != SFO_C128) return fail(SFO_E_INVALID, "unknown dtype %d", d.dtype);
+    if (!(d.dt > 0) || !std::isfinite(d.dt)) return fail(SFO_E_INVALID, "dt must be positive and finite");
+    if (!(d.hbar > 0) || !(d.mass > 0)) return fail(SFO_E_INVALID, "hbar and mass must be positive");
+    if (d.equation == SFO_DIRAC && (d.ndim != 2 || !(d.c > 0)))
+        return fail(SFO_E_INVALID, "Dirac needs ndim == 2 and c > 0");
+    int64_t ntot = 1;
+    for (int a = 0; a < d.ndim; ++a) {
+        if (!is_pow2(d.n[a])) return fail(SFO_E_INVALID, "n[%d] = %lld is not a power of two", a, (long long)d.n[a]);
+        if (!(d.xmax[a] > d.xmin[a]) || !std::isfinite(d.xmin[a]) || !std::isfinite(d.xmax[a]))
+            return fail(SFO_E_INVALID, "axis %d: need finite xmin < xmax", a);
+        const int64_t maxn = d.ndim == 1 ? kMax1DN : kMaxPassN;
+        if (d.n[a] < kMinN || d.n[a] > maxn)
+            return fail(SFO_E_UNSUPPORTED, "n[%d] = %lld outside the supported %d..%lld", a, (long long)d.n[a], kMinN,
+                        (long long)maxn);
+        ntot *= d.n[a];
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    int ndev = 0;
+    if (e == hipSuccess) e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(SFO_E_HIP, "no HIP device: %s", hipGetErrorString(e));
+
+    sfo_grid g = new sfo_grid_s;
+    g->d = d;
+    g->st = (hipStream_t)hip_stream;
+    g->ndim = d.ndim;
+    g->ncomp = d.equation == SFO_DIRAC ? 4 : 1;
+    g->ntot = ntot;
+    g->c128 = d.dtype == SFO_C128;
+    g->v0_fp64 = g->c128 || (d.flags & SFO_V0_FP64);
+    g->dv = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g->n[a] = a < d.ndim ? d.n[a] : 1;
+        g->dx[a] = a < d.ndim ? (d.xmax[a] - d.xmin[a]) / (double)d.n[a] : 0.0;
+        if (a < d.ndim) g->dv *= g->dx[a];
+    }
+    sfo_status s = SFO_OK;
+    auto guard = [&](sfo_status r) { if (r != SFO_OK) { free_grid(g); } return r; };
+    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_twiddles(g, a);
+    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_kinetic(g, a);
+    if (s != SFO_OK) return guard(s);
+    const double2 one = {1.0, 0.0};
+    hipError_t he = hipMalloc(&g->one, sizeof(double2));
+    if (he == hipSuccess) he = hipMemcpy(g->one, &one, sizeof(double2), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&g->red, sizeof(double) * (2 * kReduceBlocks + 4));
+    const size_t vbytes = (g->v0_fp64 ? sizeof(double) : sizeof(float)) * (size_t)ntot;
+    if (he == hipSuccess) he = hipMalloc(&g->V0, vbytes);
+    if (he == hipSuccess) he = hipMemset(g->V0, 0, vbytes);
+    if (he != hipSuccess)
+        return guard(fail(he == hipErrorOutOfMemory ? SFO_E_NOMEM : SFO_E_HIP, "allocation: %s", hipGetErrorString(he)));
+    *out = g;
+    return SFO_OK;
+}
+
+sfo_status sfo_destroy_grid(sfo_grid g)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    (void)hipStreamSynchronize(g->st);
+    free_grid(g);
+    return SFO_OK;
+}
+
+sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev)
+{
+    if (!g || !V0_dev) return fail(SFO_E_INVALID, "null grid or potential");
+    HIP_TRY(launch_convert_v0(V0_dev, g->V0, g->v0_fp64, g->ntot, g->st));
+    return SFO_OK;
+}
+
+sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "field table is for the Schroedinger equation");
+    if (nsteps < 0 || (nsteps > 0 && !ebar_host)) return fail(SFO_E_INVALID, "bad field table");
+    HIP_TRY(hipStreamSynchronize(g->st));
+    (void)hipFree(g->ebar_d);
+    g->ebar_d = nullptr;
+    g->ebar.assign(ebar_host, ebar_host + nsteps * g->ndim);
+    g->ebar_steps = nsteps;
+    if (nsteps > 0) {
+        for (double v : g->ebar)
+            if (!std::isfinite(v)) return fail(SFO_E_INVALID, "field table holds a non-finite value");
+        // the 1-D kernel reads the x component of each step
+        std::vector<double> ex(nsteps);
+        for (int64_t s = 0; s < nsteps; ++s) ex[s] = g->ebar[s * g->ndim];
+        HIP_TRY(hipMalloc(&g->ebar_d, sizeof(double) * nsteps));
+        HIP_TRY(hipMemcpy(g->ebar_d, ex.data(), sizeof(double) * nsteps, hipMemcpyHostToDevice));
+    }
+    return SFO_OK;
+}
+
+sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    if (g->d.equation != SFO_DIRAC) return fail(SFO_E_INVALID, "vector potential is for the Dirac equation");
+    if (nsteps < 0 || (nsteps > 0 && !abar_y_host)) return fail(SFO_E_INVALID, "bad vector-potential table");
+    HIP_TRY(hipStreamSynchronize(g->st));
+    (void)hipFree(g->abar_d);
+    g->abar_d = nullptr;
+    g->abar.assign(abar_y_host, abar_y_host + nsteps * g->n[0]);
+    g->abar_steps = nsteps;
+    if (nsteps > 0) {
+        HIP_TRY(hipMalloc(&g->abar_d, sizeof(double) * nsteps * g->n[0]));
+        HIP_TRY(hipMemcpy(g->abar_d, g->abar.data(), sizeof(double) * nsteps * g->n[0], hipMemcpyHostToDevice));
+    }
+    return SFO_OK;
+}
+
+sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nsteps)
+{
+    if (!g || !psi_dev) return fail(SFO_E_INVALID, "null grid or state");
+    sfo_status s = check_steps(g, step0, nsteps);
+    if (s) return s;
+    if (g->d.equation == SFO_DIRAC) return fail(SFO_E_UNSUPPORTED, "Dirac propagation not built yet");
+    return g->c128 ? schro_run<double>(g, psi_dev, step0, nsteps, +1) : schro_run<float>(g, psi_dev, step0, nsteps, +1);
+}
+
+sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index) { return sfo_propagate(g, psi_dev, step_index, 1); }
+
+sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps, double *dL_debar_dev,
+                       double *dL_dV0_dev)
+{
+    (void)g; (void)psi_dev; (void)g_dev; (void)step0; (void)nsteps; (void)dL_debar_dev; (void)dL_dV0_dev;
+    return fail(SFO_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host)
+{
+    if (!g || !psi_dev || !out_host) return fail(SFO_E_INVALID, "null argument");
+    const int64_t n = g->ntot * g->ncomp;
+    double *res = g->red + 2 * kReduceBlocks;
+    if (g->c128)
+        HIP_TRY(launch_norm<double>((const cx<double> *)psi_dev, n, g->red, res, g->st));
+    else
+        HIP_TRY(launch_norm<float>((const cx<float> *)psi_dev, n, g->red, res, g->st));
+    double h;
+    HIP_TRY(hipMemcpyAsync(&h, res, sizeof(double), hipMemcpyDeviceToHost, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    *out_host = h * g->dv;
+    return SFO_OK;
+}
+
+sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double *out_host)
+{
+    if (!g || !a_dev || !b_dev || !out_host) return fail(SFO_E_INVALID, "null argument");
+    const int64_t n = g->ntot * g->ncomp;
+    double *res = g->red + 2 * kReduceBlocks;
+    if (g->c128)
+        HIP_TRY(launch_overlap<double>((const cx<double> *)a_dev, (const cx<double> *)b_dev, n, g->red, res, g->st));
+    else
+        HIP_TRY(launch_overlap<float>((const cx<float> *)a_dev, (const cx<float> *)b_dev, n, g->red, res, g->st));
+    double h[2];
+    HIP_TRY(hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    out_host[0] = h[0] * g->dv;
+    out_host[1] = h[1] * g->dv;
+    return SFO_OK;
+}
+
+sfo_status sfo_profile_enable(sfo_grid g, int32_t on)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    HIP_TRY(hipStreamSynchronize(g->st));
+    prof_clear(g);
+    g->prof = on != 0;
+    return SFO_OK;
+}
+
+sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *total_ms)
+{
+    if (!g || !count || !total_ms) return fail(SFO_E_INVALID, "null argument");
+    if (kind < 0 || kind >= SFO_KERNEL_KINDS) return fail(SFO_E_INVALID, "unknown kernel kind %d", kind);
+    HIP_TRY(hipStreamSynchronize(g->st));
+    double sum = 0.0;
+    for (auto &p : g->ev[kind]) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.first, p.second));
+        sum += ms;
+    }
+    *count = (int64_t)g->ev[kind].size();
+    *total_ms = sum;
+    return SFO_OK;
+}
+
+sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign)
+{
+    if (!g || !psi_dev) return fail(SFO_E_INVALID, "null grid or state");
+    if (sign != 1 && sign != -1) return fail(SFO_E_INVALID, "sign must be -1 or +1");
+    if (g->ndim == 1 && g->n[0] > kMaxPassN)
+        return fail(SFO_E_UNSUPPORTED, "stand-alone transform supports lines up to %d points", kMaxPassN);
+    return g->c128 ? do_fft<double>(g, psi_dev, sign) : do_fft<float>(g, psi_dev, sign);
+}
+
+}  // extern "C"

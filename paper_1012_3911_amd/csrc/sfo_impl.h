@@ -1,0 +1,108 @@
+// Internal interface between the C ABI layer (sfo_api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_engine.h"
+
+namespace sfo {
+
+// Pass modes: which operations a line pass applies, in this order.
+enum : int {
+    M_INV = 1,    // inverse transform along the pass axis (first)
+    M_PHASE = 2,  // real-space potential factor (row passes only)
+    M_KIN = 8,    // momentum-space factor (column passes only)
+    M_FWD = 4,    // forward transform along the pass axis (last for rows, first for columns)
+};
+
+// Real-space phase of a row pass: theta(x) = aV * V0(x) + e . x, applied as
+// exp(-i sgn theta) (sgn = -1 for the inverse step).
+struct PhaseArgs {
+    double aV;
+    double e[3];
+    double xmin[3];
+    double dx[3];
+    int sgn;
+};
+
+// Momentum-space factor of a column pass, for element e of column `col`:
+//   K = kA[col % nA] * kB[col / nA] * kL[e]   (conjugated if sgn < 0).
+struct KinArgs {
+    const double2 *kA;
+    const double2 *kB;
+    const double2 *kL;
+    int nA;
+    int sgn;
+};
+
+// Dirac real-space factor of a row pass (4 planes):
+//   exp(-i sgn aV V0) [cos a + i sin a alpha_2],  a = sgn * aA * Abar_y(x),
+// with Abar_y(x) = ca * abar[step_a][x] + cb * abar[step_b][x].
+struct DiracPhaseArgs {
+    double aV;
+    double aA;
+    const double *abar_a;
+    const double *abar_b;
+    double ca, cb;
+    int sgn;
+};
+
+// Dirac momentum-space factor: (1/Ntot) [cos(E tau/hbar) - i sgn sin(E tau/hbar) H/E],
+// H = c alpha.(hbar k) + m c^2 beta; k from per-axis wave-number tables.
+struct DiracKinArgs {
+    const double *kx;  // nx wave numbers (FFT order)
+    const double *ky;  // ny wave numbers
+    double c, mc2, hbar, tau_over_hbar, inv_ntot;
+    int sgn;
+};
+
+// 1-D whole-run kernel arguments (one work-group per problem).
+struct Run1DArgs {
+    const double2 *kin;  // N kinetic factors (1/N folded in)
+    const double *ebar;  // per-step field integrals (1 per step) or null
+    int64_t step0, nsteps;
+    double aV_half;   // tau / (2 hbar)
+    double inv_2hbar; // 1 / (2 hbar)
+    double xmin, dx;
+    int dir;          // +1 forward steps, -1 inverse steps (last first)
+};
+
+template <typename R>
+hipError_t launch_xpass(int N, cx<R> *psi, int64_t nrows, int ny, const void *V0, bool v0_fp64,
+                        const void *tw, const PhaseArgs &ph, int mode, hipStream_t st);
+
+template <typename R>
+hipError_t launch_colpass(int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
+                          int64_t slab_stride, const void *tw, const KinArgs &kin, int mode,
+                          hipStream_t st);
+
+template <typename R>
+hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const void *V0,
+                     bool v0_fp64, const void *tw, const Run1DArgs &a, hipStream_t st);
+
+template <typename R>
+hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
+                              bool v0_fp64, const void *tw, const DiracPhaseArgs &ph, int mode,
+                              hipStream_t st);
+
+template <typename R>
+hipError_t launch_dirac_colpass(int N, cx<R> *psi, int nx, int64_t plane, const void *tw,
+                                const DiracKinArgs &kin, int mode, hipStream_t st);
+
+// FP64 reductions over n complex values: sum |a|^2 -> out[0]; or sum conj(a) b -> out[0..1].
+template <typename R>
+hipError_t launch_norm(const cx<R> *a, int64_t n, double *partials, double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_overlap(const cx<R> *a, const cx<R> *b, int64_t n, double *partials, double *out,
+                          hipStream_t st);
+
+hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t n, hipStream_t st);
+
+constexpr int kReduceBlocks = 1024;
+
+// Maximum line length of the row/column passes and of the 1-D kernel.
+constexpr int kMaxPassN = 4096;
+constexpr int kMax1DN = 8192;
+constexpr int kMinN = 64;
+
+}  // namespace sfo
