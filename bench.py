@@ -61,6 +61,7 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype=dtype, flags=flags)
     g.set_potential(wl.V0)
     g.set_field(wl.ebar)
+    plan = g.autotune(20)
     psi = torch.from_numpy(wl.psi0).to("cuda").to(g.torch_dtype).contiguous()
     n0 = g.norm(psi)
     run_steps(g, psi, warmup, wl.nsteps)
@@ -83,7 +84,7 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g.close()
     del psi
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern)
+    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, plan=plan)
 
 
 def cpu_baseline(wl, budget):
@@ -189,7 +190,8 @@ def main():
                      "c64_rel_l2_vs_c128_after_run": err_vs_c128,
                      "c128_norm_drift_per_run": res.get("c128", {}).get("drift")},
         "paths": {k: {"ms_per_step": 1e3 * v["seconds"] / args.steps,
-                      "updates_per_s": npts * args.steps / v["seconds"]} for k, v in res.items()},
+                      "updates_per_s": npts * args.steps / v["seconds"], "plan": list(v["plan"])}
+                  for k, v in res.items()},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -63,7 +63,6 @@ enum { SFO_C64 = 0, SFO_C128 = 1 };
 
 /* flags */
 enum {
-    SFO_V0_FP64 = 1u << 0, /* keep V0 in FP64 also for complex64 states (default: FP32) */
     SFO_UNFUSED = 1u << 1  /* run the paper's five-launch step (phase kernel, FFT, kinetic
                               kernel, inverse FFT, phase kernel) instead of the fused passes;
                               a reference configuration of the same kernels */
@@ -97,8 +96,10 @@ sfo_status sfo_destroy_grid(sfo_grid g);
 
 /* Copy the static potential energy V0(x) (FP64, N_points values, device
  * pointer, layout [z][y][x]) into the handle, which keeps it in FP32 for
- * complex64 states unless SFO_V0_FP64 is set, in FP64 otherwise.  The
- * caller's buffer may be freed after the stream reaches this call. */
+ * complex64 states and in FP64 for complex128 states (the phase argument is
+ * always formed in FP64).  Synchronises the stream (it also records max|V0|,
+ * which selects the shorter sin/cos series when every potential phase of a
+ * step is below 1/8 rad).  Errors: SFO_E_INVALID for a non-finite value. */
 sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev);
 
 /* Copy the per-step field integrals Ebar[step][axis] (host, FP64,
@@ -142,6 +143,19 @@ sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double 
  * exp(sign 2 pi i j m / N) along each axis, sign = -1 or +1 (the transform
  * the step uses internally; exposed for diagnostics). */
 sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign);
+
+/* Tile-shape planning.  Each line pass exists in several shapes (lines per
+ * work-group, register radix, occupancy hint).  sfo_autotune times every
+ * shape of every pass of this grid `reps` times on a scratch state the call
+ * allocates and frees, keeps the fastest, and remembers the choice for later
+ * grids of the same shape, precision and equation in this process and, if
+ * the environment variable SFO_TUNE_CACHE names a file, in that file.
+ * Synchronises the stream.  sfo_get_plan / sfo_set_plan read and force the
+ * three shape numbers (x pass, y pass, z pass); setting a shape that does not
+ * exist for the grid is SFO_E_INVALID. */
+sfo_status sfo_autotune(sfo_grid g, int32_t reps);
+sfo_status sfo_get_plan(sfo_grid g, int32_t *plan3);
+sfo_status sfo_set_plan(sfo_grid g, const int32_t *plan3);
 
 /* Kernel timing (diagnostics).  While enabled, every pass the handle launches
  * is bracketed by a pair of HIP events recorded on the handle's stream;

@@ -115,6 +115,19 @@ template <int DIR, int NR, int E, typename R> __device__ __forceinline__ cx<R> c
         return mul_quarter<DIR>(a);
     } else if constexpr (e16 == 12) {
         return mul_quarter<-DIR>(a);
+    } else if constexpr ((e16 & 3) == 2) {
+        // odd multiple of 45 degrees: W = h (sr + i si), h = sqrt(1/2), sr, si = +-1
+        constexpr double sr = cos16(e16) > 0 ? 1.0 : -1.0;
+        constexpr double si = (DIR < 0 ? -1.0 : 1.0) * (sin16(e16) > 0 ? 1.0 : -1.0);
+        const R u = sr > 0 ? (si > 0 ? a.re - a.im : a.re + a.im) : (si > 0 ? -a.re - a.im : -a.re + a.im);
+        const R w = si > 0 ? (sr > 0 ? a.re + a.im : a.re - a.im) : (sr > 0 ? -a.re + a.im : -a.re - a.im);
+        constexpr double h = 0.70710678118654752440;
+        if constexpr (sizeof(R) == 4) {
+            constexpr float hh = (float)h, hl = (float)(h - (double)hh);
+            return {__builtin_fmaf(u, hh, u * hl), __builtin_fmaf(w, hh, w * hl)};
+        } else {
+            return {u * h, w * h};
+        }
     } else {
         constexpr double wr = cos16(e16);
         constexpr double wi = (DIR < 0 ? -1.0 : 1.0) * sin16(e16);
@@ -183,9 +196,24 @@ template <int NR, int DIR, typename R> __device__ __forceinline__ void dft(cx<R>
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// LDS slot of logical element p of a line (one pad slot every 16 elements).
-__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
-__host__ __device__ constexpr int lds_line_stride(int N) { return N + N / 16 + 1; }
+// LDS placement of element p of a line during an exchange.  Bank conflicts
+// of the Stockham write pattern (stride L r between lanes) are removed by an
+// XOR swizzle of the low address bits for lines a work-group owns alone
+// (RowMap: the map stays inside aligned blocks of 32 and is a bijection, so a
+// line needs exactly N slots) and by one pad slot every 8 elements for
+// lines interleaved C-wise (ColMap: lane c of a column group is at offset c).
+// The swizzle shifts were chosen with a 64-bank, 4-byte-word model of the
+// LDS over the write and read patterns of every stage for N = 256..4096.
+template <typename R, int RAD> struct RowMap {
+    static constexpr int SH = RAD == 8 ? 3 : 4;
+    static constexpr int MASK = sizeof(R) == 4 ? 31 : 15;
+    __device__ static int at(int p) { return p ^ ((p >> SH) & MASK); }
+    static constexpr int slots(int N) { return N; }
+};
+template <int C> struct ColMap {
+    __device__ static int at(int p) { return (p + (p >> 3)) * C; }
+    static constexpr int slots(int N) { return (N + N / 8) * C; }
+};
 
 // Shape of an N-point line transform with RAD values per thread.
 template <int N, int RAD> struct LineShape {
@@ -197,12 +225,17 @@ template <int N, int RAD> struct LineShape {
     static constexpr int NST = NFULL + (REM > 1 ? 1 : 0);
     static constexpr int radix(int s) { return (REM > 1 && s == 0) ? REM : RV; }
     static constexpr int span(int s) { return s == 0 ? 1 : span(s - 1) * radix(s - 1); }
-    static constexpr int LDS = lds_line_stride(N);       // complex slots per line in LDS
+    // Stage twiddle table: stage s (span L > 1, radix r) stores W_{L r}^{j k} at
+    // tw_offset(s) + (j - 1) L + k, j = 1..r-1, k = 0..L-1, so that the lanes of a
+    // wave (consecutive k) read consecutive entries.
+    static constexpr int tw_offset(int s) { return s <= 1 ? 0 : tw_offset(s - 1) + (radix(s - 1) - 1) * span(s - 1); }
+    static constexpr int TW_SIZE = tw_offset(NST);
 };
 
 // One Stockham stage S of an N-point transform (see the file comment).
-// v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in line.
-template <typename R, int N, int RAD, int DIR, int S, int NV>
+// v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in
+// line; tw: the stage twiddle table of this (N, RAD).
+template <typename R, int N, int RAD, int DIR, int S, class MAP, int NV>
 __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
 {
     using Sh = LineShape<N, RAD>;
@@ -213,7 +246,7 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
     constexpr int RV = Sh::RV, T = Sh::T;
     constexpr int r = Sh::radix(S), L = Sh::span(S), NB = RV / r;
     constexpr bool last = (S == Sh::NST - 1);
-    constexpr int TWS = N / (L * r);  // table stride of W_{L r}
+    constexpr int TWO = Sh::tw_offset(S);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         cx<R> u[r];
@@ -223,7 +256,7 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         const int k = b & (L - 1);
         if constexpr (L > 1) {
 #pragma unroll
-            for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, j * k * TWS);
+            for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L + k);
         }
         dft<r, DIR>(u);
         if constexpr (last) {
@@ -232,23 +265,25 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         } else {
             const int base = (b / L) * (L * r) + k;
 #pragma unroll
-            for (int m = 0; m < r; ++m) sh[lds_pad(base + m * L)] = u[m];
+            for (int m = 0; m < r; ++m) sh[MAP::at(base + m * L)] = u[m];
         }
     }
     if constexpr (!last) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[m] = sh[lds_pad(t + m * T)];
+        for (int m = 0; m < RV; ++m) v[m] = sh[MAP::at(t + m * T)];
         __syncthreads();
     }
 }
 
-template <typename R, int N, int RAD, int DIR, int S = 0, int NV>
+// Full N-point transform of the thread's cyclic values (direction DIR), with
+// the LDS exchanges placed by MAP (RowMap<R, RAD> or ColMap<C>).
+template <typename R, int N, int RAD, int DIR, class MAP, int S = 0, int NV>
 __device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
 {
     if constexpr (S < LineShape<N, RAD>::NST) {
-        fft_stage<R, N, RAD, DIR, S>(v, sh, t, tw);
-        fft_line<R, N, RAD, DIR, S + 1>(v, sh, t, tw);
+        fft_stage<R, N, RAD, DIR, S, MAP>(v, sh, t, tw);
+        fft_line<R, N, RAD, DIR, MAP, S + 1>(v, sh, t, tw);
     }
 }
 

@@ -1,9 +1,15 @@
 // C ABI layer: validation, library-owned device tables, and the pass
 // sequences of a split-operator run.  See include/sfo.h for the contract.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -50,15 +56,17 @@ struct sfo_grid_s {
     double dx[3] = {0, 0, 0};
     double dv = 1;
     bool c128 = false;
-    bool v0_fp64 = false;
     void *V0 = nullptr;
+    double v0max = 0.0;   // max |V0|, for the bound of the potential phase
+    int row_var = 0;      // tile variants chosen for the x pass and the y/z passes
+    int col_var[3] = {0, 0, 0};
     std::vector<double> ebar;  // host copy, nsteps x ndim
     double *ebar_d = nullptr;  // device copy (1-D kernel reads it)
     int64_t ebar_steps = 0;
     std::vector<double> abar;  // Dirac: nsteps x n[0]
     double *abar_d = nullptr;
     int64_t abar_steps = 0;
-    void *tw[3] = {nullptr, nullptr, nullptr};     // per-axis twiddle tables
+    void *tw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // per-axis stage twiddles, radix 8 / 16
     double2 *kin[3] = {nullptr, nullptr, nullptr}; // per-axis kinetic factors (1/Ntot in axis 0)
     double *kvec[3] = {nullptr, nullptr, nullptr}; // per-axis wave numbers (Dirac)
     double2 *one = nullptr;                        // {1, 0}
@@ -91,7 +99,8 @@ void free_grid(sfo_grid g)
     (void)hipFree(g->ebar_d);
     (void)hipFree(g->abar_d);
     for (int a = 0; a < 3; ++a) {
-        (void)hipFree(g->tw[a]);
+        (void)hipFree(g->tw[a][0]);
+        (void)hipFree(g->tw[a][1]);
         (void)hipFree(g->kin[a]);
         (void)hipFree(g->kvec[a]);
     }
@@ -144,26 +153,46 @@ void unit_root(int64_t j, int64_t n, double &c, double &s)
     s = -ss;  // forward root: exp(-i angle)
 }
 
+// Stage twiddle tables of axis a for radix 8 and 16 (the layout of
+// LineShape::tw_offset): stage (radix r, span L > 1) holds W_{L r}^{j k} at
+// offset + (j - 1) L + k.
 sfo_status make_twiddles(sfo_grid g, int a)
 {
-    const int64_t n = g->n[a];
-    if (g->c128) {
-        std::vector<TwEntry<double>> h(n);
-        for (int64_t j = 0; j < n; ++j) unit_root(j, n, h[j].r, h[j].i);
-        HIP_TRY(hipMalloc(&g->tw[a], sizeof(TwEntry<double>) * n));
-        HIP_TRY(hipMemcpy(g->tw[a], h.data(), sizeof(TwEntry<double>) * n, hipMemcpyHostToDevice));
-    } else {
-        std::vector<TwEntry<float>> h(n);
-        for (int64_t j = 0; j < n; ++j) {
-            double c, s;
-            unit_root(j, n, c, s);
-            h[j].hr = (float)c;
-            h[j].hi = (float)s;
-            h[j].lr = (float)(c - (double)h[j].hr);
-            h[j].li = (float)(s - (double)h[j].hi);
+    const int n = (int)g->n[a];
+    for (int ri = 0; ri < 2; ++ri) {
+        const int rad = ri == 0 ? 8 : 16;
+        int radix[16], span[16], nst = 0;
+        line_stages(n, rad, radix, span, &nst);
+        std::vector<double> cr, ci;
+        for (int s = 0; s < nst; ++s) {
+            const int r = radix[s], L = span[s];
+            if (L == 1) continue;
+            for (int j = 1; j < r; ++j)
+                for (int k = 0; k < L; ++k) {
+                    double c, sn;
+                    unit_root((int64_t)j * k * (n / (L * r)), n, c, sn);
+                    cr.push_back(c);
+                    ci.push_back(sn);
+                }
         }
-        HIP_TRY(hipMalloc(&g->tw[a], sizeof(TwEntry<float>) * n));
-        HIP_TRY(hipMemcpy(g->tw[a], h.data(), sizeof(TwEntry<float>) * n, hipMemcpyHostToDevice));
+        const size_t cnt = cr.size() ? cr.size() : 1;
+        if (cr.empty()) { cr.push_back(1.0); ci.push_back(0.0); }
+        if (g->c128) {
+            std::vector<TwEntry<double>> h(cnt);
+            for (size_t i = 0; i < cnt; ++i) { h[i].r = cr[i]; h[i].i = ci[i]; }
+            HIP_TRY(hipMalloc(&g->tw[a][ri], sizeof(TwEntry<double>) * cnt));
+            HIP_TRY(hipMemcpy(g->tw[a][ri], h.data(), sizeof(TwEntry<double>) * cnt, hipMemcpyHostToDevice));
+        } else {
+            std::vector<TwEntry<float>> h(cnt);
+            for (size_t i = 0; i < cnt; ++i) {
+                h[i].hr = (float)cr[i];
+                h[i].hi = (float)ci[i];
+                h[i].lr = (float)(cr[i] - (double)h[i].hr);
+                h[i].li = (float)(ci[i] - (double)h[i].hi);
+            }
+            HIP_TRY(hipMalloc(&g->tw[a][ri], sizeof(TwEntry<float>) * cnt));
+            HIP_TRY(hipMemcpy(g->tw[a][ri], h.data(), sizeof(TwEntry<float>) * cnt, hipMemcpyHostToDevice));
+        }
     }
     return SFO_OK;
 }
@@ -241,6 +270,11 @@ PhaseArgs phase_args(const sfo_grid g, int64_t sa, int64_t sb, int sgn)
         p.dx[a] = a < g->ndim ? g->dx[a] : 0.0;
     }
     p.sgn = sgn;
+    p.small = (std::fabs(p.aV) * g->v0max <= 0.125) ? 1 : 0;
+    double bound = std::fabs(p.aV) * g->v0max;
+    for (int a = 0; a < g->ndim; ++a)
+        bound += std::fabs(p.e[a]) * std::max(std::fabs(g->d.xmin[a]), std::fabs(g->d.xmax[a]));
+    p.small32 = bound <= 0.125 ? 1 : 0;
     return p;
 }
 
@@ -248,8 +282,8 @@ template <typename R> sfo_status schro_xpass(sfo_grid g, void *psi, int64_t sa, 
 {
     const PhaseArgs ph = phase_args(g, sa, sb, sgn);
     HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
-        return launch_xpass<R>((int)g->n[0], (cx<R> *)psi, g->n[1] * g->n[2], (int)g->n[1], g->V0, g->v0_fp64,
-                               g->tw[0], ph, mode, g->st);
+        return launch_xpass<R>(g->row_var, (int)g->n[0], (cx<R> *)psi, g->n[1] * g->n[2], (int)g->n[1], g->V0,
+                               (const void *const *)g->tw[0], ph, mode, g->st);
     }));
     return SFO_OK;
 }
@@ -262,21 +296,25 @@ template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, int mode
     if (g->ndim == 2) {
         KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
         HIP_TRY(timed(g, SFO_KERNEL_COLUMN,
-                      [&] { return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, 1, 0, g->tw[1], k, mode, g->st); }));
+                      [&] { return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, 1, 0, (const void *const *)g->tw[1], k,
+                                                     mode, g->st); }));
     } else {
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
         KinArgs none{g->one, g->one, g->one, 1, 1};
         KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, g->tw[1], none, M_FWD, g->st);
+                return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, (const void *const *)g->tw[1], none,
+                                         M_FWD, g->st);
             }));
         HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
-            return launch_colpass<R>((int)nz, (cx<R> *)psi, nx * ny, nx * ny, 1, 0, g->tw[2], k, mode, g->st);
+            return launch_colpass<R>(g->col_var[2], (int)nz, (cx<R> *)psi, nx * ny, nx * ny, 1, 0, (const void *const *)g->tw[2], k, mode,
+                                     g->st);
         }));
         if (mode & M_INV)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>((int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, g->tw[1], none, M_INV, g->st);
+                return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, (const void *const *)g->tw[1], none,
+                                         M_INV, g->st);
             }));
     }
     return SFO_OK;
@@ -311,7 +349,7 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
         a.dx = g->dx[0];
         a.dir = dir;
         HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
-            return launch_1d<R>((int)g->n[0], (cx<R> *)psi, 1, g->ntot, g->V0, g->v0_fp64, g->tw[0], a, g->st);
+            return launch_1d<R>((int)g->n[0], (cx<R> *)psi, 1, g->ntot, g->V0, g->tw[0][1], a, g->st);
         }));
         return SFO_OK;
     }
@@ -341,6 +379,127 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
     return SFO_OK;
 }
 
+// ------------------------------------------------------------- planning --
+// Tile shapes chosen by timing, remembered per grid shape for the process
+// and optionally in a text file named by SFO_TUNE_CACHE (one line per shape:
+// "<key> <row> <y-pass> <z-pass>").
+std::mutex g_plan_mu;
+std::map<std::string, std::vector<int>> g_plans;
+bool g_plans_loaded = false;
+
+std::string plan_key(const sfo_grid g)
+{
+    std::ostringstream k;
+    k << (g->c128 ? "c128" : "c64") << ":" << (g->d.equation == SFO_DIRAC ? "dirac" : "schro") << ":" << g->n[0]
+      << "x" << g->n[1] << "x" << g->n[2];
+    return k.str();
+}
+
+void load_plan_file()
+{
+    if (g_plans_loaded) return;
+    g_plans_loaded = true;
+    const char *path = std::getenv("SFO_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string key;
+    int a, b, c;
+    while (f >> key >> a >> b >> c) g_plans[key] = {a, b, c};
+}
+
+void store_plan(const std::string &key, const std::vector<int> &p)
+{
+    g_plans[key] = p;
+    const char *path = std::getenv("SFO_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << p[0] << " " << p[1] << " " << p[2] << "\n";
+}
+
+template <typename R> bool plan_valid(const sfo_grid g, const int *p)
+{
+    if (!xpass_variant_ok<R>(p[0], (int)g->n[0])) return false;
+    if (g->ndim >= 2 && !colpass_variant_ok<R>(p[1], (int)g->n[1], g->n[0])) return false;
+    if (g->ndim == 3 && !colpass_variant_ok<R>(p[2], (int)g->n[2], g->n[0] * g->n[1])) return false;
+    return true;
+}
+
+// Milliseconds of `reps` launches of fn (after two warm-up launches); -1 if a launch fails.
+template <typename F> double time_launches(sfo_grid g, hipEvent_t a, hipEvent_t b, int reps, F &&fn)
+{
+    for (int i = 0; i < 2; ++i)
+        if (fn() != hipSuccess) return -1.0;
+    if (hipEventRecord(a, g->st) != hipSuccess) return -1.0;
+    for (int i = 0; i < reps; ++i)
+        if (fn() != hipSuccess) return -1.0;
+    if (hipEventRecord(b, g->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
+    return ms;
+}
+
+template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
+{
+    const size_t bytes = sizeof(cx<R>) * (size_t)g->ntot * g->ncomp;
+    void *scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, bytes));
+    hipEvent_t ea = nullptr, eb = nullptr;
+    hipError_t he = hipMemsetAsync(scratch, 0, bytes, g->st);
+    if (he == hipSuccess) he = hipEventCreate(&ea);
+    if (he == hipSuccess) he = hipEventCreate(&eb);
+    if (he != hipSuccess) {
+        (void)hipFree(scratch);
+        if (ea) (void)hipEventDestroy(ea);
+        return fail(SFO_E_HIP, "autotune setup: %s", hipGetErrorString(he));
+    }
+    cx<R> *psi = (cx<R> *)scratch;
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const PhaseArgs ph = phase_args(g, -1, 0, +1);
+    double best = 1e30;
+    for (int v = 0; v < kNumRowVariants; ++v) {
+        if (!xpass_variant_ok<R>(v, (int)nx)) continue;
+        const double ms = time_launches(g, ea, eb, reps, [&] {
+            return launch_xpass<R>(v, (int)nx, psi, ny * nz, (int)ny, g->V0, (const void *const *)g->tw[0], ph, M_INV | M_PHASE | M_FWD,
+                                   g->st);
+        });
+        if (ms >= 0 && ms < best) { best = ms; g->row_var = v; }
+    }
+    for (int ax = 1; ax < g->ndim; ++ax) {
+        const int64_t n = g->n[ax];
+        const int64_t ncols = ax == 1 ? nx : nx * ny;
+        const int nslab = (ax == 1 && g->ndim == 3) ? (int)nz : 1;
+        const bool kinetic = ax == g->ndim - 1;
+        KinArgs k{g->kin[0], ax == 2 ? g->kin[1] : g->one, g->kin[ax], (int)nx, 1};
+        KinArgs none{g->one, g->one, g->one, 1, 1};
+        best = 1e30;
+        for (int v = 0; v < kNumColVariants; ++v) {
+            if (!colpass_variant_ok<R>(v, (int)n, ncols)) continue;
+            const double ms = time_launches(g, ea, eb, reps, [&] {
+                return launch_colpass<R>(v, (int)n, psi, ncols, ncols, nslab, nx * ny, (const void *const *)g->tw[ax], kinetic ? k : none,
+                                         kinetic ? (M_FWD | M_KIN | M_INV) : M_FWD, g->st);
+            });
+            if (ms >= 0 && ms < best) { best = ms; g->col_var[ax] = v; }
+        }
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    (void)hipFree(scratch);
+    return SFO_OK;
+}
+
+// Default tile shapes before any tuning: the first shape in table order that
+// exists for each pass of this grid.
+template <typename R> void default_plan(sfo_grid g)
+{
+    for (int v = 0; v < kNumRowVariants; ++v)
+        if (xpass_variant_ok<R>(v, (int)g->n[0])) { g->row_var = v; break; }
+    for (int ax = 1; ax < g->ndim; ++ax) {
+        const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
+        for (int v = 0; v < kNumColVariants; ++v)
+            if (colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) { g->col_var[ax] = v; break; }
+    }
+}
+
 template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
 {
     const int mode = sign < 0 ? M_FWD : M_INV;
@@ -348,14 +507,16 @@ template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
         cx<R> *p = (cx<R> *)psi + c * g->ntot;
         PhaseArgs ph{};
         ph.sgn = 1;
-        HIP_TRY(launch_xpass<R>((int)g->n[0], p, g->n[1] * g->n[2], (int)g->n[1], g->V0, g->v0_fp64, g->tw[0], ph,
+        HIP_TRY(launch_xpass<R>(g->row_var, (int)g->n[0], p, g->n[1] * g->n[2], (int)g->n[1], g->V0, (const void *const *)g->tw[0], ph,
                                 mode, g->st));
         if (g->ndim >= 2) {
             const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
             KinArgs none{g->one, g->one, g->one, 1, 1};
-            HIP_TRY(launch_colpass<R>((int)ny, p, nx, nx, (int)nz, nx * ny, g->tw[1], none, mode, g->st));
+            HIP_TRY(launch_colpass<R>(g->col_var[1], (int)ny, p, nx, nx, (int)nz, nx * ny,
+                                      (const void *const *)g->tw[1], none, mode, g->st));
             if (g->ndim == 3)
-                HIP_TRY(launch_colpass<R>((int)nz, p, nx * ny, nx * ny, 1, 0, g->tw[2], none, mode, g->st));
+                HIP_TRY(launch_colpass<R>(g->col_var[2], (int)nz, p, nx * ny, nx * ny, 1, 0,
+                                          (const void *const *)g->tw[2], none, mode, g->st));
         }
     }
     return SFO_OK;
@@ -407,13 +568,16 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     g->ncomp = d.equation == SFO_DIRAC ? 4 : 1;
     g->ntot = ntot;
     g->c128 = d.dtype == SFO_C128;
-    g->v0_fp64 = g->c128 || (d.flags & SFO_V0_FP64);
     g->dv = 1.0;
     for (int a = 0; a < 3; ++a) {
         g->n[a] = a < d.ndim ? d.n[a] : 1;
         g->dx[a] = a < d.ndim ? (d.xmax[a] - d.xmin[a]) / (double)d.n[a] : 0.0;
         if (a < d.ndim) g->dv *= g->dx[a];
     }
+    if (g->c128)
+        default_plan<double>(g);
+    else
+        default_plan<float>(g);
     sfo_status s = SFO_OK;
     auto guard = [&](sfo_status r) { if (r != SFO_OK) { free_grid(g); } return r; };
     for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_twiddles(g, a);
@@ -423,7 +587,7 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     hipError_t he = hipMalloc(&g->one, sizeof(double2));
     if (he == hipSuccess) he = hipMemcpy(g->one, &one, sizeof(double2), hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMalloc(&g->red, sizeof(double) * (2 * kReduceBlocks + 4));
-    const size_t vbytes = (g->v0_fp64 ? sizeof(double) : sizeof(float)) * (size_t)ntot;
+    const size_t vbytes = (g->c128 ? sizeof(double) : sizeof(float)) * (size_t)ntot;
     if (he == hipSuccess) he = hipMalloc(&g->V0, vbytes);
     if (he == hipSuccess) he = hipMemset(g->V0, 0, vbytes);
     if (he != hipSuccess)
@@ -443,7 +607,14 @@ sfo_status sfo_destroy_grid(sfo_grid g)
 sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev)
 {
     if (!g || !V0_dev) return fail(SFO_E_INVALID, "null grid or potential");
-    HIP_TRY(launch_convert_v0(V0_dev, g->V0, g->v0_fp64, g->ntot, g->st));
+    HIP_TRY(launch_convert_v0(V0_dev, g->V0, g->c128, g->ntot, g->st));
+    double *res = g->red + 2 * kReduceBlocks;
+    HIP_TRY(launch_absmax(V0_dev, g->ntot, g->red, res, g->st));
+    double m = 0.0;
+    HIP_TRY(hipMemcpyAsync(&m, res, sizeof(double), hipMemcpyDeviceToHost, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    if (!std::isfinite(m)) return fail(SFO_E_INVALID, "potential holds a non-finite value");
+    g->v0max = m;
     return SFO_OK;
 }
 
@@ -534,6 +705,55 @@ sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double 
     HIP_TRY(hipStreamSynchronize(g->st));
     out_host[0] = h[0] * g->dv;
     out_host[1] = h[1] * g->dv;
+    return SFO_OK;
+}
+
+sfo_status sfo_autotune(sfo_grid g, int32_t reps)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    if (reps < 1 || reps > 10000) return fail(SFO_E_INVALID, "reps must be in 1..10000");
+    if (g->ndim == 1) return SFO_OK;  // the whole-run 1-D kernel has a single shape
+    const std::string key = plan_key(g);
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        load_plan_file();
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            const int p[3] = {it->second[0], it->second[1], it->second[2]};
+            if (g->c128 ? plan_valid<double>(g, p) : plan_valid<float>(g, p)) {
+                g->row_var = p[0];
+                g->col_var[1] = p[1];
+                g->col_var[2] = p[2];
+                return SFO_OK;
+            }
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(g->st));
+    sfo_status s = g->c128 ? autotune_impl<double>(g, reps) : autotune_impl<float>(g, reps);
+    if (s) return s;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    store_plan(key, {g->row_var, g->col_var[1], g->col_var[2]});
+    return SFO_OK;
+}
+
+sfo_status sfo_get_plan(sfo_grid g, int32_t *plan)
+{
+    if (!g || !plan) return fail(SFO_E_INVALID, "null argument");
+    plan[0] = g->row_var;
+    plan[1] = g->col_var[1];
+    plan[2] = g->col_var[2];
+    return SFO_OK;
+}
+
+sfo_status sfo_set_plan(sfo_grid g, const int32_t *plan)
+{
+    if (!g || !plan) return fail(SFO_E_INVALID, "null argument");
+    const int p[3] = {plan[0], g->ndim >= 2 ? plan[1] : 0, g->ndim == 3 ? plan[2] : 0};
+    if (!(g->c128 ? plan_valid<double>(g, p) : plan_valid<float>(g, p)))
+        return fail(SFO_E_INVALID, "tile shapes (%d, %d, %d) do not exist for this grid", p[0], p[1], p[2]);
+    g->row_var = p[0];
+    g->col_var[1] = p[1];
+    g->col_var[2] = p[2];
     return SFO_OK;
 }
 

@@ -1,0 +1,44 @@
+// Instantiations of the strided column passes for complex64 and complex128.
+#include "pass_kernels.h"
+
+namespace sfo {
+
+template <typename R>
+hipError_t launch_colpass(int variant, int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
+                          int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st)
+{
+#define CALL(n)                                                                                       \
+    col_dispatch<R, n>(variant, psi, ncols, stride, nslab, slab_stride, tw, kin, mode, st,           \
+                       std::make_index_sequence<kNumColVariants>{})
+    SFO_SWITCH_PASS_N(N, CALL)
+#undef CALL
+}
+
+template <typename R, int N, size_t... I> bool col_ok_n(int v, std::index_sequence<I...>)
+{
+    bool ok = false;
+    ((v == (int)I ? (ok = col_variant_ok<R, N, (int)I>(), 0) : 0), ...);
+    return ok;
+}
+
+template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols)
+{
+    if (variant < 0 || variant >= kNumColVariants) return false;
+    if (ncols % kColVariants[variant].cols) return false;
+    switch (N) {
+#define CASE(n) case n: return col_ok_n<R, n>(variant, std::make_index_sequence<kNumColVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return false;
+    }
+}
+
+template bool colpass_variant_ok<float>(int, int, int64_t);
+template bool colpass_variant_ok<double>(int, int, int64_t);
+
+template hipError_t launch_colpass<float>(int, int, cx<float> *, int64_t, int64_t, int, int64_t, const void *const *,
+                                          const KinArgs &, int, hipStream_t);
+template hipError_t launch_colpass<double>(int, int, cx<double> *, int64_t, int64_t, int, int64_t, const void *const *,
+                                           const KinArgs &, int, hipStream_t);
+
+}  // namespace sfo

@@ -23,6 +23,8 @@ struct PhaseArgs {
     double xmin[3];
     double dx[3];
     int sgn;
+    int small;    // |aV V0| <= 1/8 everywhere: short FP64 sin/cos series suffice
+    int small32;  // |aV V0 + e.x| <= 1/8 everywhere: complex64 may form the factor in FP32
 };
 
 // Momentum-space factor of a column pass, for element e of column `col`:
@@ -67,22 +69,48 @@ struct Run1DArgs {
     int dir;          // +1 forward steps, -1 inverse steps (last first)
 };
 
+// Tile shapes the planner chooses from (index = variant number).  Row
+// passes: register radix, threads per work-group (rows = threads / (N/radix)),
+// minimum waves per SIMD the register allocation must allow.  Column
+// passes: register radix, adjacent lines per work-group, waves per SIMD.
+struct RowVariant {
+    int rad, threads, wpe;
+};
+struct ColVariant {
+    int rad, cols, wpe;
+};
+constexpr RowVariant kRowVariants[] = {{16, 256, 1}, {16, 128, 1}, {16, 512, 1}, {16, 256, 3},
+                                       {16, 256, 4}, {8, 256, 1},  {8, 512, 1},  {8, 256, 4}};
+constexpr ColVariant kColVariants[] = {{16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2},
+                                       {16, 2, 4}, {8, 8, 1},  {8, 4, 1},  {8, 2, 4}};
+constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);
+constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
+
+// tw[0], tw[1]: the stage twiddle tables of the line length for radix 8 and 16.
 template <typename R>
-hipError_t launch_xpass(int N, cx<R> *psi, int64_t nrows, int ny, const void *V0, bool v0_fp64,
-                        const void *tw, const PhaseArgs &ph, int mode, hipStream_t st);
+hipError_t launch_xpass(int variant, int N, cx<R> *psi, int64_t nrows, int ny, const void *V0,
+                        const void *const *tw, const PhaseArgs &ph, int mode, hipStream_t st);
 
 template <typename R>
-hipError_t launch_colpass(int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
-                          int64_t slab_stride, const void *tw, const KinArgs &kin, int mode,
+hipError_t launch_colpass(int variant, int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
+                          int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode,
                           hipStream_t st);
+
+// Host copy of the stage layout of LineShape<N, RAD>: (radix, span) per stage.
+void line_stages(int N, int RAD, int *radix, int *span, int *nst);
+
+// Whether a variant exists for this line length and precision (and, for
+// columns, divides the number of lines).
+template <typename R> bool xpass_variant_ok(int variant, int N);
+template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols);
 
 template <typename R>
 hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const void *V0,
-                     bool v0_fp64, const void *tw, const Run1DArgs &a, hipStream_t st);
+                     const void *tw, const Run1DArgs &a, hipStream_t st);
 
 template <typename R>
 hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
-                              bool v0_fp64, const void *tw, const DiracPhaseArgs &ph, int mode,
+                              const void *tw, const DiracPhaseArgs &ph, int mode,
                               hipStream_t st);
 
 template <typename R>
@@ -97,6 +125,9 @@ hipError_t launch_overlap(const cx<R> *a, const cx<R> *b, int64_t n, double *par
                           hipStream_t st);
 
 hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t n, hipStream_t st);
+
+// max |src| over n values into *out (device), for the potential-phase bound.
+hipError_t launch_absmax(const double *src, int64_t n, double *partials, double *out, hipStream_t st);
 
 constexpr int kReduceBlocks = 1024;
 

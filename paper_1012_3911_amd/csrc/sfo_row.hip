@@ -1,0 +1,42 @@
+// Instantiations of the row (x) pass for complex64 and complex128.
+#include "pass_kernels.h"
+
+namespace sfo {
+
+template <typename R>
+hipError_t launch_xpass(int variant, int N, cx<R> *psi, int64_t nrows, int ny, const void *V0, const void *const *tw,
+                        const PhaseArgs &ph, int mode, hipStream_t st)
+{
+#define CALL(n) \
+    row_dispatch<R, n>(variant, psi, nrows, ny, V0, tw, ph, mode, st, std::make_index_sequence<kNumRowVariants>{})
+    SFO_SWITCH_PASS_N(N, CALL)
+#undef CALL
+}
+
+template <typename R, int N, size_t... I> bool row_ok_n(int v, std::index_sequence<I...>)
+{
+    bool ok = false;
+    ((v == (int)I ? (ok = row_variant_ok<R, N, (int)I>(), 0) : 0), ...);
+    return ok;
+}
+
+template <typename R> bool xpass_variant_ok(int variant, int N)
+{
+    if (variant < 0 || variant >= kNumRowVariants) return false;
+    switch (N) {
+#define CASE(n) case n: return row_ok_n<R, n>(variant, std::make_index_sequence<kNumRowVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return false;
+    }
+}
+
+template bool xpass_variant_ok<float>(int, int);
+template bool xpass_variant_ok<double>(int, int);
+
+template hipError_t launch_xpass<float>(int, int, cx<float> *, int64_t, int, const void *, const void *const *,
+                                        const PhaseArgs &, int, hipStream_t);
+template hipError_t launch_xpass<double>(int, int, cx<double> *, int64_t, int, const void *, const void *const *,
+                                         const PhaseArgs &, int, hipStream_t);
+
+}  // namespace sfo

@@ -19,7 +19,6 @@ LIB_PATH = os.path.join(_HERE, "libsfo.so")
 SFO_OK, SFO_E_INVALID, SFO_E_UNSUPPORTED, SFO_E_NOMEM, SFO_E_HIP, SFO_E_STATE = 0, -1, -2, -3, -4, -5
 SCHRODINGER, DIRAC = 0, 1
 C64, C128 = 0, 1
-V0_FP64 = 1 << 0
 UNFUSED = 1 << 1
 
 _STATUS_NAMES = {0: "SFO_OK", -1: "SFO_E_INVALID", -2: "SFO_E_UNSUPPORTED", -3: "SFO_E_NOMEM",
@@ -53,7 +52,7 @@ _lib = None
 
 EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_field",
            "sfo_set_vector_potential", "sfo_step", "sfo_propagate", "sfo_adjoint", "sfo_norm",
-           "sfo_overlap", "sfo_fft", "sfo_profile_enable", "sfo_profile_read", "sfo_last_error",
+           "sfo_overlap", "sfo_fft", "sfo_autotune", "sfo_get_plan", "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_last_error",
            "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
@@ -80,6 +79,9 @@ def load_library(path: str = LIB_PATH):
         "sfo_norm": [P, P, P],
         "sfo_overlap": [P, P, P, P],
         "sfo_fft": [P, P, I32],
+        "sfo_autotune": [P, I32],
+        "sfo_get_plan": [P, P],
+        "sfo_set_plan": [P, P],
         "sfo_profile_enable": [P, I32],
         "sfo_profile_read": [P, I32, P, P],
     }
@@ -214,6 +216,21 @@ class Grid:
         out = (ctypes.c_double * 2)()
         _check(_lib.sfo_overlap(self._h, self._state(a, "a"), self._state(b, "b"), out), "sfo_overlap")
         return complex(out[0], out[1])
+
+    def autotune(self, reps: int = 20):
+        _check(_lib.sfo_autotune(self._h, int(reps)), "sfo_autotune")
+        return self.plan
+
+    @property
+    def plan(self):
+        out = (ctypes.c_int32 * 3)()
+        _check(_lib.sfo_get_plan(self._h, out), "sfo_get_plan")
+        return tuple(out)
+
+    @plan.setter
+    def plan(self, p):
+        arr = (ctypes.c_int32 * 3)(*[int(x) for x in p])
+        _check(_lib.sfo_set_plan(self._h, arr), "sfo_set_plan")
 
     def profile(self, on: bool = True):
         _check(_lib.sfo_profile_enable(self._h, 1 if on else 0), "sfo_profile_enable")

@@ -117,6 +117,47 @@ def test_3d_wells(orc, dtype):
     assert rel_l2(got, ref) < (C128_TOL if dtype == "c128" else C64_TOL)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_every_tile_shape(orc, dtype):
+    """Every row-pass and column-pass tile shape the planner may choose gives the oracle's
+    result (anisotropic 256 x 512 grid, 20 steps); autotune picks one of them."""
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    n, lo, hi = (256, 512), (-25.6, -51.2), (25.6, 51.2)
+    X, Y = W.mesh(n, lo, hi)
+    wl = W.Workload("t", "schrodinger", n, lo, hi, 0.02, 20, -1.0 / np.sqrt(X**2 + Y**2 + 1.0),
+                    W.gaussian(n, lo, hi, (0.5, -0.5), 0.9, (0.3, 0.1)),
+                    ebar=np.tile([[0.002, -0.001]], (20, 1)))
+    ref = oracle_run(orc, wl)
+    tol = C128_TOL if dtype == "c128" else C64_TOL
+    g = make_grid(wl, dtype)
+    base = g.plan
+    tried = 0
+    for kind in (0, 1):
+        for v in range(16):
+            p = list(base)
+            p[kind] = v
+            try:
+                g.plan = p
+            except sfo.SfoError:
+                continue
+            psi = to_device(wl.psi0, dtype)
+            g.propagate(psi, 0, wl.nsteps)
+            torch.cuda.synchronize()
+            err = rel_l2(psi.cpu().numpy(), ref)
+            assert err < tol, (kind, v, err)
+            tried += 1
+    assert tried >= 8
+    g.plan = base
+    chosen = g.autotune(3)
+    psi = to_device(wl.psi0, dtype)
+    g.propagate(psi, 0, wl.nsteps)
+    torch.cuda.synchronize()
+    assert rel_l2(psi.cpu().numpy(), ref) < tol, chosen
+    g.close()
+
+
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 def test_step_equals_propagate(orc, ndim):
     if ndim == 1:
