@@ -38,39 +38,95 @@ template <int N, int RAD, int THREADS> struct RowTile {
     static constexpr int NT = ROWS * Sh::T;
 };
 
+// Sum of v over the work-group (all threads), FP64, deterministic order;
+// every thread returns the total.  red: 16 x 3 doubles of LDS.
+__device__ __forceinline__ void block_sum3(double (&v)[3], double (*red)[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        for (int off = 32; off > 0; off >>= 1) v[a] += __shfl_xor(v[a], off, 64);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) red[w][a] = v[a];
+    __syncthreads();
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += red[i][a];
+        v[a] = s;
+    }
+    __syncthreads();
+}
+
+// Work-group partial moments -> part[blockIdx.x]; the last group to finish
+// sums all partials in a fixed order into out[0..2] and re-arms the counter.
+__device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], double *part, unsigned *count,
+                                          double *out)
+{
+    block_sum3(v, red);
+    __shared__ unsigned last;
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) part[3 * blockIdx.x + a] = v[a];
+        __threadfence();
+        last = atomicAdd(count, 1u) == gridDim.x * gridDim.y - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        const unsigned nb = gridDim.x * gridDim.y;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (unsigned i = threadIdx.x; i < nb; i += blockDim.x)
+            for (int a = 0; a < 3; ++a) s[a] += __builtin_nontemporal_load(part + 3 * i + a);
+        block_sum3(s, red);
+        if (threadIdx.x == 0) {
+            for (int a = 0; a < 3; ++a) out[a] = s[a];
+            *count = 0u;
+        }
+    }
+}
+
 // --------------------------------------------------------------- row pass --
-// One work-group holds ROWS rows of N points; thread t of a row owns the
-// cyclic elements x = t + m T.  Global access is contiguous along the row.
-// The potential factor exp(-i sgn [aV V0(x) + e.x]) is built from a per-point
-// exp(-i sgn aV V0) and the separable field factor exp(-i sgn e.x), whose
+// One work-group holds ROWS rows of N points of each of NS states (NS = 2:
+// the state and its adjoint, walked back together); thread t of a row owns
+// the cyclic elements x = t + m T.  Global access is contiguous along the
+// row.  The potential factor exp(-i sgn [aV V0(x) + e.x]) is computed once
+// per point and applied to every state.  In FP64 it is a per-point
+// exp(-i sgn aV V0) times the separable field factor exp(-i sgn e.x), whose
 // x-dependence along the thread's elements is a geometric sequence (ratio
 // exp(-i sgn e_x T dx)) advanced by FP64 complex multiplication.
-template <typename R, int N, int RAD, int THREADS, int WPE>
+// M_GRAD (NS = 2) additionally forms b = Im(conj(g) psi) at this step
+// boundary in real space: acc += w b (the dL/dV0 accumulator) and the
+// moments sum_x (x b, y b, z b) reduced over the grid into ga.mom.
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS>
 __global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_xpass(cx<R> *__restrict__ psi, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
-        PhaseArgs ph, int mode)
+k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
+        PhaseArgs ph, GradArgs ga, int mode)
 {
     using Sh = LineShape<N, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, THREADS>::ROWS;
     using Map = RowMap<R, RAD>;
     __shared__ cx<R> lds[ROWS * Map::slots(N)];
+    __shared__ double red[16][3];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int64_t row = (int64_t)blockIdx.x * ROWS + line;
-    cx<R> *p = psi + row * N;
     cx<R> *sh = lds + line * Map::slots(N);
-    cx<R> v[RV];
+    cx<R> v[NS][RV];
     VStore<R> vv[RV];
 #pragma unroll
-    for (int m = 0; m < RV; ++m) v[m] = p[t + m * T];
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][row * N + t + m * T];
     if (mode & M_PHASE) {
         // issue the potential loads now; they complete under the inverse transform
         const VStore<R> *vr = V0 + row * N;
 #pragma unroll
         for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
     }
-    if (mode & M_INV) fft_line<R, N, RAD, +1, Map>(v, sh, t, tw);
+    if (mode & M_INV)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+    const int64_t y = row % ny, z = row / ny;
     if (mode & M_PHASE) {
-        const int64_t y = row % ny, z = row / ny;
         const double sg = (double)ph.sgn;
         const double base = ph.e[1] * (ph.xmin[1] + (double)y * ph.dx[1]) +
                             ph.e[2] * (ph.xmin[2] + (double)z * ph.dx[2]);
@@ -90,11 +146,14 @@ k_xpass(cx<R> *__restrict__ psi, int ny, const VStore<R> *__restrict__ V0, const
                 pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
                 pc = __builtin_fmaf(pc, x2, -0.5f);
                 const float cm = pc * x2;
-                const float a = (float)v[m].re, b = (float)v[m].im;
-                const float dr = __builtin_fmaf(a, cm, b * sn);
-                const float di = __builtin_fmaf(b, cm, -(a * sn));
-                v[m].re = (R)(a + dr);
-                v[m].im = (R)(b + di);
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const float a = (float)v[q][m].re, b = (float)v[q][m].im;
+                    const float dr = __builtin_fmaf(a, cm, b * sn);
+                    const float di = __builtin_fmaf(b, cm, -(a * sn));
+                    v[q][m].re = (R)(a + dr);
+                    v[q][m].im = (R)(b + di);
+                }
             }
         } else {
             double s0, c0, s1, c1;
@@ -109,7 +168,9 @@ k_xpass(cx<R> *__restrict__ psi, int ny, const VStore<R> *__restrict__ V0, const
                 if (ph.small) sincos_small(th, sv, cv);
                 else sincos_fp64(th, sv, cv);
                 // (cv - i sv) (fr + i fi)
-                v[m] = mul_phase(v[m], cv * fr + sv * fi, cv * fi - sv * fr);
+                const double tr = cv * fr + sv * fi, ti = cv * fi - sv * fr;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], tr, ti);
                 const double nr = fr * wr - fi * wi;
                 fi = fr * wi + fi * wr;
                 fr = nr;
@@ -117,22 +178,45 @@ k_xpass(cx<R> *__restrict__ psi, int ny, const VStore<R> *__restrict__ V0, const
             }
         }
     }
-    if (mode & M_FWD) fft_line<R, N, RAD, -1, Map>(v, sh, t, tw);
+    if (NS == 2 && (mode & M_GRAD)) {
+        double mom[3] = {0.0, 0.0, 0.0};
+        double sb = 0.0;
 #pragma unroll
-    for (int m = 0; m < RV; ++m) p[t + m * T] = v[m];
+        for (int m = 0; m < RV; ++m) {
+            const int x = t + m * T;
+            const cx<R> ps = v[0][m], gq = v[NS - 1][m];
+            const double b = (double)gq.re * (double)ps.im - (double)gq.im * (double)ps.re;
+            if (ga.acc) {
+                double *ap = ga.acc + row * N + x;
+                *ap = (ga.acc_init ? 0.0 : *ap) + ga.wacc * b;
+            }
+            sb += b;
+            mom[0] += (ph.xmin[0] + (double)x * ph.dx[0]) * b;
+        }
+        mom[1] = (ph.xmin[1] + (double)y * ph.dx[1]) * sb;
+        mom[2] = (ph.xmin[2] + (double)z * ph.dx[2]) * sb;
+        grid_sum3(mom, red, ga.part, ga.count, ga.mom);
+    }
+    if (mode & M_FWD)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) S.p[q][row * N + t + m * T] = v[q][m];
 }
 
 // ------------------------------------------------------------ column pass --
 // Lines run along a strided axis (stride elements apart); one work-group
-// holds C adjacent lines so that each global access moves C contiguous
-// values.  Thread (t, c) owns elements t + m T of line c.  Work-groups are
-// dispatched round-robin over the 8 XCDs; the group index is remapped so
-// that consecutive column groups, which share cache lines, run on the same
-// XCD (and so share its L2) at about the same time.
-template <typename R, int N, int RAD, int C, int WPE>
+// holds C adjacent lines (of each of NS states) so that each global access
+// moves C contiguous values.  Thread (t, c) owns elements t + m T of line c.
+// Work-groups are dispatched round-robin over the 8 XCDs; the group index is
+// remapped so that consecutive column groups, which share cache lines, run
+// on the same XCD (and so share its L2) at about the same time.
+template <typename R, int N, int RAD, int C, int WPE, int NS>
 __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_colpass(cx<R> *__restrict__ psi, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw,
-          KinArgs kin, int mode)
+k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw, KinArgs kin,
+          int mode)
 {
     using Sh = LineShape<N, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV;
@@ -144,12 +228,16 @@ k_colpass(cx<R> *__restrict__ psi, int64_t stride, int64_t slab_stride, const Tw
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
     const unsigned gx = L % gridDim.x, slab = L / gridDim.x;
     const int64_t col = (int64_t)gx * C + c;
-    cx<R> *p = psi + (int64_t)slab * slab_stride + col;
+    const int64_t off = (int64_t)slab * slab_stride + col;
     cx<R> *sh = lds + c;
-    cx<R> v[RV];
+    cx<R> v[NS][RV];
 #pragma unroll
-    for (int m = 0; m < RV; ++m) v[m] = p[(int64_t)(t + m * T) * stride];
-    if (mode & M_FWD) fft_line<R, N, RAD, -1, Map>(v, sh, t, tw);
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][off + (int64_t)(t + m * T) * stride];
+    if (mode & M_FWD)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
     if (mode & M_KIN) {
         const double2 a = kin.kA[col % kin.nA], b = kin.kB[col / kin.nA];
         const double kcr = a.x * b.x - a.y * b.y, kci = a.x * b.y + a.y * b.x;
@@ -157,12 +245,17 @@ k_colpass(cx<R> *__restrict__ psi, int64_t stride, int64_t slab_stride, const Tw
         for (int m = 0; m < RV; ++m) {
             const double2 l = kin.kL[t + m * T];
             const double kr = kcr * l.x - kci * l.y, ki = kcr * l.y + kci * l.x;
-            v[m] = mul_phase(v[m], kr, (double)kin.sgn * ki);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)kin.sgn * ki);
         }
     }
-    if (mode & M_INV) fft_line<R, N, RAD, +1, Map>(v, sh, t, tw);
+    if (mode & M_INV)
 #pragma unroll
-    for (int m = 0; m < RV; ++m) p[(int64_t)(t + m * T) * stride] = v[m];
+        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) S.p[q][off + (int64_t)(t + m * T) * stride] = v[q][m];
 }
 
 // ------------------------------------------------------ variant dispatch --
@@ -174,9 +267,9 @@ template <typename R, int N, int V> constexpr bool row_variant_ok()
     return Tl::NT <= 1024 && Tl::ROWS * RowMap<R, rv.rad>::slots(N) * (int)sizeof(cx<R>) <= 160 * 1024;
 }
 
-template <typename R, int N, int V>
-hipError_t row_launch(cx<R> *psi, int64_t nrows, int ny, const void *V0, const void *const *tws,
-                      const PhaseArgs &ph, int mode, hipStream_t st)
+template <typename R, int N, int V, int NS>
+hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0, const void *const *tws,
+                      const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st)
 {
     if constexpr (!row_variant_ok<R, N, V>()) {
         return hipErrorInvalidValue;
@@ -186,24 +279,25 @@ hipError_t row_launch(cx<R> *psi, int64_t nrows, int ny, const void *V0, const v
         using Tl = RowTile<N, rv.rad, rv.threads>;
         if (nrows % Tl::ROWS) {
             // fewer rows than a work-group holds (a single 1-D line): one row per group
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 0>), dim3((unsigned)nrows),
-                               dim3(LineShape<N, rv.rad>::T), 0, st, psi, ny, (const VStore<R> *)V0,
-                               (const TwEntry<R> *)tw, ph, mode);
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS>), dim3((unsigned)nrows),
+                               dim3(LineShape<N, rv.rad>::T), 0, st, S, ny, (const VStore<R> *)V0,
+                               (const TwEntry<R> *)tw, ph, ga, mode);
         } else {
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe>), dim3((unsigned)(nrows / Tl::ROWS)),
-                               dim3(Tl::NT), 0, st, psi, ny, (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph,
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS>), dim3((unsigned)(nrows / Tl::ROWS)),
+                               dim3(Tl::NT), 0, st, S, ny, (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga,
                                mode);
         }
         return hipGetLastError();
     }
 }
 
-template <typename R, int N, size_t... I>
-hipError_t row_dispatch(int var, cx<R> *psi, int64_t nrows, int ny, const void *V0, const void *const *tw,
-                        const PhaseArgs &ph, int mode, hipStream_t st, std::index_sequence<I...>)
+template <typename R, int N, int NS, size_t... I>
+hipError_t row_dispatch(int var, const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0,
+                        const void *const *tw, const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st,
+                        std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
-    ((var == (int)I ? (r = row_launch<R, N, (int)I>(psi, nrows, ny, V0, tw, ph, mode, st), 0) : 0), ...);
+    ((var == (int)I ? (r = row_launch<R, N, (int)I, NS>(S, nrows, ny, V0, tw, ph, ga, mode, st), 0) : 0), ...);
     return r;
 }
 
@@ -215,8 +309,8 @@ template <typename R, int N, int V> constexpr bool col_variant_ok()
            ColMap<cv.cols>::slots(N) * (int)sizeof(cx<R>) <= 160 * 1024;
 }
 
-template <typename R, int N, int V>
-hipError_t col_launch(cx<R> *psi, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
+template <typename R, int N, int V, int NS>
+hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
                       const void *const *tws, const KinArgs &kin, int mode, hipStream_t st)
 {
     if constexpr (!col_variant_ok<R, N, V>()) {
@@ -225,19 +319,20 @@ hipError_t col_launch(cx<R> *psi, int64_t ncols, int64_t stride, int nslab, int6
         constexpr ColVariant cv = kColVariants[V];
         const void *tw = tws[cv.rad == 8 ? 0 : 1];
         if (ncols % cv.cols) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_colpass<R, N, cv.rad, cv.cols, cv.wpe>), dim3((unsigned)(ncols / cv.cols), (unsigned)nslab),
-                           dim3(cv.cols * LineShape<N, cv.rad>::T), 0, st, psi, stride, slab_stride,
-                           (const TwEntry<R> *)tw, kin, mode);
+        hipLaunchKernelGGL((k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>),
+                           dim3((unsigned)(ncols / cv.cols), (unsigned)nslab), dim3(cv.cols * LineShape<N, cv.rad>::T),
+                           0, st, S, stride, slab_stride, (const TwEntry<R> *)tw, kin, mode);
         return hipGetLastError();
     }
 }
 
-template <typename R, int N, size_t... I>
-hipError_t col_dispatch(int var, cx<R> *psi, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
-                        const void *const *tw, const KinArgs &kin, int mode, hipStream_t st, std::index_sequence<I...>)
+template <typename R, int N, int NS, size_t... I>
+hipError_t col_dispatch(int var, const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab,
+                        int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st,
+                        std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
-    ((var == (int)I ? (r = col_launch<R, N, (int)I>(psi, ncols, stride, nslab, slab_stride, tw, kin, mode, st), 0)
+    ((var == (int)I ? (r = col_launch<R, N, (int)I, NS>(S, ncols, stride, nslab, slab_stride, tw, kin, mode, st), 0)
                     : 0),
      ...);
     return r;

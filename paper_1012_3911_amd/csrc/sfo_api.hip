@@ -71,6 +71,12 @@ struct sfo_grid_s {
     double *kvec[3] = {nullptr, nullptr, nullptr}; // per-axis wave numbers (Dirac)
     double2 *one = nullptr;                        // {1, 0}
     double *red = nullptr;                         // reduction partials + result
+    // adjoint scratch: per-boundary moments, per-work-group partials, a group counter
+    double *mom = nullptr;
+    int64_t mom_cap = 0;
+    double *part = nullptr;
+    int64_t part_cap = 0;
+    unsigned *count = nullptr;
     // kernel timing: event pairs per kernel kind while profiling is on
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
@@ -106,6 +112,9 @@ void free_grid(sfo_grid g)
     }
     (void)hipFree(g->one);
     (void)hipFree(g->red);
+    (void)hipFree(g->mom);
+    (void)hipFree(g->part);
+    (void)hipFree(g->count);
     delete g;
 }
 
@@ -278,43 +287,50 @@ PhaseArgs phase_args(const sfo_grid g, int64_t sa, int64_t sb, int sgn)
     return p;
 }
 
-template <typename R> sfo_status schro_xpass(sfo_grid g, void *psi, int64_t sa, int64_t sb, int sgn, int mode)
+// Row pass over one state (adj == null) or a state and its adjoint.
+template <typename R>
+sfo_status schro_xpass(sfo_grid g, void *psi, void *adj, int64_t sa, int64_t sb, int sgn, int mode,
+                       const GradArgs &ga = GradArgs{})
 {
     const PhaseArgs ph = phase_args(g, sa, sb, sgn);
+    const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
     HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
-        return launch_xpass<R>(g->row_var, (int)g->n[0], (cx<R> *)psi, g->n[1] * g->n[2], (int)g->n[1], g->V0,
-                               (const void *const *)g->tw[0], ph, mode, g->st);
+        return launch_xpass<R>(g->row_var, (int)g->n[0], adj ? 2 : 1, S, g->n[1] * g->n[2], (int)g->n[1], g->V0,
+                               (const void *const *)g->tw[0], ph, ga, mode, g->st);
     }));
     return SFO_OK;
 }
 
 // Forward/inverse transforms and the kinetic factor along the non-x axes.
 // mode: M_FWD, M_INV, M_KIN combinations (in the order FWD, KIN, INV).
-template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, int mode, int sgn)
+template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
+    const int ns = adj ? 2 : 1;
+    const void *const *tw1 = (const void *const *)g->tw[1];
+    const void *const *tw2 = (const void *const *)g->tw[2];
     if (g->ndim == 2) {
         KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
-        HIP_TRY(timed(g, SFO_KERNEL_COLUMN,
-                      [&] { return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, 1, 0, (const void *const *)g->tw[1], k,
-                                                     mode, g->st); }));
+        HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
+            return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, 1, 0, tw1, k, mode, g->st);
+        }));
     } else {
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
         KinArgs none{g->one, g->one, g->one, 1, 1};
         KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, (const void *const *)g->tw[1], none,
-                                         M_FWD, g->st);
+                return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
+                                         g->st);
             }));
         HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
-            return launch_colpass<R>(g->col_var[2], (int)nz, (cx<R> *)psi, nx * ny, nx * ny, 1, 0, (const void *const *)g->tw[2], k, mode,
-                                     g->st);
+            return launch_colpass<R>(g->col_var[2], (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, mode, g->st);
         }));
         if (mode & M_INV)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>(g->col_var[1], (int)ny, (cx<R> *)psi, nx, nx, (int)nz, nx * ny, (const void *const *)g->tw[1], none,
-                                         M_INV, g->st);
+                return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_INV,
+                                         g->st);
             }));
     }
     return SFO_OK;
@@ -358,21 +374,21 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
         // the paper's sequence: phase kernel, FFT, kinetic kernel, inverse FFT, phase kernel
         for (int64_t j = 0; j < nsteps; ++j) {
             const int64_t st = step_of(j);
-            if ((s = schro_xpass<R>(g, psi, -1, st, dir, M_PHASE))) return s;
-            if ((s = schro_xpass<R>(g, psi, -1, -1, dir, M_FWD))) return s;
-            if ((s = schro_colpasses<R>(g, psi, M_FWD, dir))) return s;
-            if ((s = schro_colpasses<R>(g, psi, M_KIN, dir))) return s;
-            if ((s = schro_colpasses<R>(g, psi, M_INV, dir))) return s;
-            if ((s = schro_xpass<R>(g, psi, -1, -1, dir, M_INV))) return s;
-            if ((s = schro_xpass<R>(g, psi, st, -1, dir, M_PHASE))) return s;
+            if ((s = schro_xpass<R>(g, psi, nullptr, -1, st, dir, M_PHASE))) return s;
+            if ((s = schro_xpass<R>(g, psi, nullptr, -1, -1, dir, M_FWD))) return s;
+            if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD, dir))) return s;
+            if ((s = schro_colpasses<R>(g, psi, nullptr, M_KIN, dir))) return s;
+            if ((s = schro_colpasses<R>(g, psi, nullptr, M_INV, dir))) return s;
+            if ((s = schro_xpass<R>(g, psi, nullptr, -1, -1, dir, M_INV))) return s;
+            if ((s = schro_xpass<R>(g, psi, nullptr, st, -1, dir, M_PHASE))) return s;
         }
         return SFO_OK;
     }
-    if ((s = schro_xpass<R>(g, psi, -1, step_of(0), dir, M_PHASE | M_FWD))) return s;
+    if ((s = schro_xpass<R>(g, psi, nullptr, -1, step_of(0), dir, M_PHASE | M_FWD))) return s;
     for (int64_t j = 0; j < nsteps; ++j) {
-        if ((s = schro_colpasses<R>(g, psi, M_FWD | M_KIN | M_INV, dir))) return s;
+        if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD | M_KIN | M_INV, dir))) return s;
         const bool more = j + 1 < nsteps;
-        if ((s = schro_xpass<R>(g, psi, step_of(j), more ? step_of(j + 1) : -1, dir,
+        if ((s = schro_xpass<R>(g, psi, nullptr, step_of(j), more ? step_of(j + 1) : -1, dir,
                                 M_INV | M_PHASE | (more ? M_FWD : 0))))
             return s;
     }
@@ -459,8 +475,8 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
     for (int v = 0; v < kNumRowVariants; ++v) {
         if (!xpass_variant_ok<R>(v, (int)nx)) continue;
         const double ms = time_launches(g, ea, eb, reps, [&] {
-            return launch_xpass<R>(v, (int)nx, psi, ny * nz, (int)ny, g->V0, (const void *const *)g->tw[0], ph, M_INV | M_PHASE | M_FWD,
-                                   g->st);
+            return launch_xpass<R>(v, (int)nx, 1, StatePtrs<R>{{psi, nullptr}}, ny * nz, (int)ny, g->V0,
+                                   (const void *const *)g->tw[0], ph, GradArgs{}, M_INV | M_PHASE | M_FWD, g->st);
         });
         if (ms >= 0 && ms < best) { best = ms; g->row_var = v; }
     }
@@ -475,7 +491,8 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         for (int v = 0; v < kNumColVariants; ++v) {
             if (!colpass_variant_ok<R>(v, (int)n, ncols)) continue;
             const double ms = time_launches(g, ea, eb, reps, [&] {
-                return launch_colpass<R>(v, (int)n, psi, ncols, ncols, nslab, nx * ny, (const void *const *)g->tw[ax], kinetic ? k : none,
+                return launch_colpass<R>(v, (int)n, 1, StatePtrs<R>{{psi, nullptr}}, ncols, ncols, nslab, nx * ny,
+                                         (const void *const *)g->tw[ax], kinetic ? k : none,
                                          kinetic ? (M_FWD | M_KIN | M_INV) : M_FWD, g->st);
             });
             if (ms >= 0 && ms < best) { best = ms; g->col_var[ax] = v; }
@@ -500,6 +517,75 @@ template <typename R> void default_plan(sfo_grid g)
     }
 }
 
+// Reverse sweep (see include/sfo.h, sfo_adjoint).  Boundary n of the run
+// (n = 0..nsteps, state psi_{step0+n}) contributes b_n = Im(conj(g_n) psi_n):
+//   dL/dV0 += (tau/2hbar) w_n b_n,  w_n = 1 at the two ends and 2 inside,
+//   mom[n] = sum_x (x, y, z) b_n,  dL/dEbar[s] = (mom[s+1] + mom[s]) / (2 hbar).
+template <typename R>
+sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV)
+{
+    const int64_t need_mom = 3 * (nsteps + 1);
+    if (g->mom_cap < need_mom) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->mom);
+        g->mom = nullptr;
+        HIP_TRY(hipMalloc(&g->mom, sizeof(double) * need_mom));
+        g->mom_cap = need_mom;
+    }
+    const int64_t nrows = g->n[1] * g->n[2];
+    if (g->ndim >= 2 && g->part_cap < 3 * nrows) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->part);
+        g->part = nullptr;
+        HIP_TRY(hipMalloc(&g->part, sizeof(double) * 3 * nrows));
+        g->part_cap = 3 * nrows;
+    }
+    if (!g->count) {
+        HIP_TRY(hipMalloc(&g->count, sizeof(unsigned)));
+        HIP_TRY(hipMemset(g->count, 0, sizeof(unsigned)));
+    }
+    const double wbase = g->d.dt / (2.0 * g->d.hbar);
+    if (g->ndim == 1) {
+        Run1DArgs a{};
+        a.kin = g->kin[0];
+        a.ebar = g->ebar_steps ? g->ebar_d : nullptr;
+        a.step0 = step0;
+        a.nsteps = nsteps;
+        a.aV_half = g->d.dt / (2.0 * g->d.hbar);
+        a.inv_2hbar = 1.0 / (2.0 * g->d.hbar);
+        a.xmin = g->d.xmin[0];
+        a.dx = g->dx[0];
+        a.dir = -1;
+        HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
+            return launch_1d_adjoint<R>((int)g->n[0], (cx<R> *)psi, (cx<R> *)gv, g->V0, g->tw[0][1], a, wbase, dV,
+                                        g->mom, g->st);
+        }));
+    } else {
+        GradArgs ga{};
+        ga.acc = dV;
+        ga.part = g->part;
+        ga.count = g->count;
+        sfo_status s;
+        auto st_of = [&](int64_t j) { return step0 + j; };
+        ga.wacc = wbase;
+        ga.acc_init = 1;
+        ga.mom = g->mom + 3 * nsteps;
+        const int first = nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD;
+        if ((s = schro_xpass<R>(g, psi, gv, -1, nsteps > 0 ? st_of(nsteps - 1) : -1, -1, first, ga))) return s;
+        for (int64_t j = nsteps - 1; j >= 0; --j) {
+            if ((s = schro_colpasses<R>(g, psi, gv, M_FWD | M_KIN | M_INV, -1))) return s;
+            ga.acc_init = 0;
+            ga.wacc = (j > 0 ? 2.0 : 1.0) * wbase;
+            ga.mom = g->mom + 3 * j;
+            if ((s = schro_xpass<R>(g, psi, gv, st_of(j), j > 0 ? st_of(j - 1) : -1, -1,
+                                    M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), ga)))
+                return s;
+        }
+    }
+    if (dE) HIP_TRY(launch_ebar_grad(g->mom, nsteps, g->ndim, 1.0 / (2.0 * g->d.hbar), dE, g->st));
+    return SFO_OK;
+}
+
 template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
 {
     const int mode = sign < 0 ? M_FWD : M_INV;
@@ -507,15 +593,16 @@ template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
         cx<R> *p = (cx<R> *)psi + c * g->ntot;
         PhaseArgs ph{};
         ph.sgn = 1;
-        HIP_TRY(launch_xpass<R>(g->row_var, (int)g->n[0], p, g->n[1] * g->n[2], (int)g->n[1], g->V0, (const void *const *)g->tw[0], ph,
-                                mode, g->st));
+        const StatePtrs<R> S{{p, nullptr}};
+        HIP_TRY(launch_xpass<R>(g->row_var, (int)g->n[0], 1, S, g->n[1] * g->n[2], (int)g->n[1], g->V0,
+                                (const void *const *)g->tw[0], ph, GradArgs{}, mode, g->st));
         if (g->ndim >= 2) {
             const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
             KinArgs none{g->one, g->one, g->one, 1, 1};
-            HIP_TRY(launch_colpass<R>(g->col_var[1], (int)ny, p, nx, nx, (int)nz, nx * ny,
+            HIP_TRY(launch_colpass<R>(g->col_var[1], (int)ny, 1, S, nx, nx, (int)nz, nx * ny,
                                       (const void *const *)g->tw[1], none, mode, g->st));
             if (g->ndim == 3)
-                HIP_TRY(launch_colpass<R>(g->col_var[2], (int)nz, p, nx * ny, nx * ny, 1, 0,
+                HIP_TRY(launch_colpass<R>(g->col_var[2], (int)nz, 1, S, nx * ny, nx * ny, 1, 0,
                                           (const void *const *)g->tw[2], none, mode, g->st));
         }
     }
@@ -671,8 +758,13 @@ sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index) { return sfo_
 sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps, double *dL_debar_dev,
                        double *dL_dV0_dev)
 {
-    (void)g; (void)psi_dev; (void)g_dev; (void)step0; (void)nsteps; (void)dL_debar_dev; (void)dL_dV0_dev;
-    return fail(SFO_E_UNSUPPORTED, "adjoint not built yet");
+    if (!g || !psi_dev || !g_dev) return fail(SFO_E_INVALID, "null grid or state");
+    if (psi_dev == g_dev) return fail(SFO_E_INVALID, "psi and g must be distinct buffers");
+    sfo_status s = check_steps(g, step0, nsteps);
+    if (s) return s;
+    if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the Schroedinger equation");
+    return g->c128 ? schro_adjoint<double>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev)
+                   : schro_adjoint<float>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev);
 }
 
 sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host)

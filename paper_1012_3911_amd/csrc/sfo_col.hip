@@ -4,12 +4,19 @@
 namespace sfo {
 
 template <typename R>
-hipError_t launch_colpass(int variant, int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
+hipError_t launch_colpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab,
                           int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st)
 {
+    if (ns == 2) {
 #define CALL(n)                                                                                       \
-    col_dispatch<R, n>(variant, psi, ncols, stride, nslab, slab_stride, tw, kin, mode, st,           \
-                       std::make_index_sequence<kNumColVariants>{})
+    col_dispatch<R, n, 2>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st,          \
+                          std::make_index_sequence<kNumColVariants>{})
+        SFO_SWITCH_PASS_N(N, CALL)
+#undef CALL
+    }
+#define CALL(n)                                                                                       \
+    col_dispatch<R, n, 1>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st,          \
+                          std::make_index_sequence<kNumColVariants>{})
     SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
 }
@@ -36,9 +43,9 @@ template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols)
 template bool colpass_variant_ok<float>(int, int, int64_t);
 template bool colpass_variant_ok<double>(int, int, int64_t);
 
-template hipError_t launch_colpass<float>(int, int, cx<float> *, int64_t, int64_t, int, int64_t, const void *const *,
-                                          const KinArgs &, int, hipStream_t);
-template hipError_t launch_colpass<double>(int, int, cx<double> *, int64_t, int64_t, int, int64_t, const void *const *,
-                                           const KinArgs &, int, hipStream_t);
+template hipError_t launch_colpass<float>(int, int, int, const StatePtrs<float> &, int64_t, int64_t, int, int64_t,
+                                          const void *const *, const KinArgs &, int, hipStream_t);
+template hipError_t launch_colpass<double>(int, int, int, const StatePtrs<double> &, int64_t, int64_t, int, int64_t,
+                                           const void *const *, const KinArgs &, int, hipStream_t);
 
 }  // namespace sfo

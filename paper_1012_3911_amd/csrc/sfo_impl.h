@@ -13,6 +13,23 @@ enum : int {
     M_PHASE = 2,  // real-space potential factor (row passes only)
     M_KIN = 8,    // momentum-space factor (column passes only)
     M_FWD = 4,    // forward transform along the pass axis (last for rows, first for columns)
+    M_GRAD = 16,  // adjoint partials at a step boundary (row passes with two states)
+};
+
+// The states a pass transforms together: p[0] alone, or the state p[0] and
+// its adjoint p[1] during the reverse sweep.
+template <typename R> struct StatePtrs {
+    cx<R> *p[2];
+};
+
+// Gradient partials of a row pass at one step boundary (see k_xpass).
+struct GradArgs {
+    double *acc;       // dL/dV0 accumulator (FP64, one per point) or null
+    double wacc;       // weight of this boundary in acc
+    int acc_init;      // 1: overwrite acc instead of adding
+    double *part;      // per-work-group partial moments, 3 per group
+    unsigned *count;   // groups finished (0 on entry; the last group resets it)
+    double *mom;       // out: sum_x (x, y, z) b over the grid
 };
 
 // Real-space phase of a row pass: theta(x) = aV * V0(x) + e . x, applied as
@@ -88,13 +105,22 @@ constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 
 // tw[0], tw[1]: the stage twiddle tables of the line length for radix 8 and 16.
 template <typename R>
-hipError_t launch_xpass(int variant, int N, cx<R> *psi, int64_t nrows, int ny, const void *V0,
-                        const void *const *tw, const PhaseArgs &ph, int mode, hipStream_t st);
+hipError_t launch_xpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t nrows, int ny,
+                        const void *V0, const void *const *tw, const PhaseArgs &ph, const GradArgs &ga,
+                        int mode, hipStream_t st);
 
 template <typename R>
-hipError_t launch_colpass(int variant, int N, cx<R> *psi, int64_t ncols, int64_t stride, int nslab,
-                          int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode,
+hipError_t launch_colpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t ncols, int64_t stride,
+                          int nslab, int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode,
                           hipStream_t st);
+
+template <typename R>
+hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a,
+                             double wbase, double *acc, double *mom, hipStream_t st);
+
+// dL/dEbar[s][a] = (mom[s+1][a] + mom[s][a]) * scale for s < nsteps (mom: (nsteps+1) x 3).
+hipError_t launch_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out,
+                            hipStream_t st);
 
 // Host copy of the stage layout of LineShape<N, RAD>: (radix, span) per stage.
 void line_stages(int N, int RAD, int *radix, int *span, int *nst);

@@ -7,9 +7,10 @@
 // inverse y-transform).  A 3-D step adds a forward and an inverse y-pass
 // around the z-pass that carries the kinetic factor.  A 1-D line of up to
 // 8192 points stays in one work-group's registers and LDS for the whole run.
+#include <algorithm>
 #include <type_traits>
 
-#include "sfo_impl.h"
+#include "pass_kernels.h"
 
 namespace sfo {
 
@@ -67,6 +68,92 @@ __global__ void __launch_bounds__((LineShape<N, RAD>::T))
     }
 #pragma unroll
     for (int m = 0; m < RV; ++m) p[t + m * T] = v[m];
+}
+
+// ------------------------------------------------------------ 1-D adjoint --
+// Reverse sweep of a 1-D run: the state psi and its adjoint g are walked back
+// together with the exact inverse step (conjugated factors, last step first),
+// as the forward whole-run kernel does with dir = -1.  At every step boundary
+// n (psi_n, g_n in real space) it forms b_n = Im(conj(g_n) psi_n): the dL/dV0
+// accumulator (registers) gains w_n b_n and mom[n] receives sum_x x b_n.
+template <typename R, typename VT, int N, int RAD>
+__global__ void __launch_bounds__((LineShape<N, RAD>::T))
+    k_1d_adjoint(cx<R> *__restrict__ psi, cx<R> *__restrict__ gv, const VT *__restrict__ V0,
+                 const TwEntry<R> *__restrict__ tw, Run1DArgs a, double wbase, double *acc_out, double *mom)
+{
+    using Sh = LineShape<N, RAD>;
+    using Map = RowMap<R, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    __shared__ cx<R> sh[Map::slots(N)];
+    __shared__ double red[16][3];
+    const int t = threadIdx.x;
+    cx<R> v[2][RV];
+    double acc[RV];
+#pragma unroll
+    for (int m = 0; m < RV; ++m) {
+        v[0][m] = psi[t + m * T];
+        v[1][m] = gv[t + m * T];
+        acc[m] = 0.0;
+    }
+    auto step_of = [&](int64_t s) { return a.step0 + a.nsteps - 1 - s; };
+    auto field = [&](int64_t st) { return a.ebar ? a.ebar[st] : 0.0; };
+    auto grad = [&](int64_t bidx, double w) {
+        double mo[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const double b = (double)v[1][m].re * (double)v[0][m].im - (double)v[1][m].im * (double)v[0][m].re;
+            acc[m] += w * b;
+            mo[0] += (a.xmin + (double)(t + m * T) * a.dx) * b;
+        }
+        block_sum3(mo, red);
+        if (t == 0)
+            for (int q = 0; q < 3; ++q) mom[3 * bidx + q] = mo[q];
+    };
+    auto potential = [&](double av, double e) {
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const int x = t + m * T;
+            const double th = -(av * (double)V0[x] + e * (a.xmin + (double)x * a.dx));
+            double sn, cs;
+            sincos_fp64(th, sn, cs);
+            v[0][m] = mul_phase(v[0][m], cs, -sn);
+            v[1][m] = mul_phase(v[1][m], cs, -sn);
+        }
+    };
+    grad(a.nsteps, wbase);
+    if (a.nsteps > 0) potential(a.aV_half, field(step_of(0)) * a.inv_2hbar);
+#pragma unroll 1
+    for (int64_t s = 0; s < a.nsteps; ++s) {
+        __asm__ __volatile__("" ::: "memory");
+        for (int q = 0; q < 2; ++q) {
+            fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+#pragma unroll
+            for (int m = 0; m < RV; ++m) {
+                const double2 k = a.kin[t + m * T];
+                v[q][m] = mul_phase(v[q][m], k.x, -k.y);
+            }
+            fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        }
+        const bool more = s + 1 < a.nsteps;
+        potential(a.aV_half * (more ? 2.0 : 1.0),
+                  (field(step_of(s)) + (more ? field(step_of(s + 1)) : 0.0)) * a.inv_2hbar);
+        grad(a.nsteps - 1 - s, (more ? 2.0 : 1.0) * wbase);
+    }
+#pragma unroll
+    for (int m = 0; m < RV; ++m) {
+        psi[t + m * T] = v[0][m];
+        gv[t + m * T] = v[1][m];
+        if (acc_out) acc_out[t + m * T] = acc[m];
+    }
+}
+
+__global__ void k_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps * ndim; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / ndim;
+        const int a = (int)(i % ndim);
+        out[i] = (mom[3 * (s + 1) + a] + mom[3 * s + a]) * scale;
+    }
 }
 
 // ------------------------------------------------------------- reductions --
@@ -224,6 +311,35 @@ hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const vo
 #undef CALL
 }
 
+template <typename R, typename VT, int N>
+static hipError_t adj1d_n(cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a, double wbase,
+                          double *acc, double *mom, hipStream_t st)
+{
+    constexpr int threads = LineShape<N, kRad>::T;
+    hipLaunchKernelGGL((k_1d_adjoint<R, VT, N, kRad>), dim3(1), dim3(threads), 0, st, psi, gv, (const VT *)V0,
+                       (const TwEntry<R> *)tw, a, wbase, acc, mom);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a,
+                             double wbase, double *acc, double *mom, hipStream_t st)
+{
+    using VT = typename std::conditional<sizeof(R) == 4, float, double>::type;
+#define CALL(n) adj1d_n<R, VT, n>(psi, gv, V0, tw, a, wbase, acc, mom, st)
+    SFO_SWITCH_1D_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out, hipStream_t st)
+{
+    if (nsteps <= 0) return hipSuccess;
+    const int64_t n = nsteps * ndim;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_ebar_grad, dim3(blocks), dim3(256), 0, st, mom, nsteps, ndim, scale, out);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_norm(const cx<R> *a, int64_t n, double *partials, double *out, hipStream_t st)
 {
@@ -257,6 +373,10 @@ template hipError_t launch_1d<float>(int, cx<float> *, int, int64_t, const void 
                                      hipStream_t);
 template hipError_t launch_1d<double>(int, cx<double> *, int, int64_t, const void *, const void *, const Run1DArgs &,
                                       hipStream_t);
+template hipError_t launch_1d_adjoint<float>(int, cx<float> *, cx<float> *, const void *, const void *,
+                                             const Run1DArgs &, double, double *, double *, hipStream_t);
+template hipError_t launch_1d_adjoint<double>(int, cx<double> *, cx<double> *, const void *, const void *,
+                                              const Run1DArgs &, double, double *, double *, hipStream_t);
 template hipError_t launch_norm<float>(const cx<float> *, int64_t, double *, double *, hipStream_t);
 template hipError_t launch_norm<double>(const cx<double> *, int64_t, double *, double *, hipStream_t);
 template hipError_t launch_overlap<float>(const cx<float> *, const cx<float> *, int64_t, double *, double *,
