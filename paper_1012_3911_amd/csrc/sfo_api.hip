@@ -586,6 +586,80 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
     return SFO_OK;
 }
 
+// ----------------------------------------------------------------- Dirac --
+DiracPhaseArgs dirac_phase_args(const sfo_grid g, int64_t sa, int64_t sb, int sgn)
+{
+    DiracPhaseArgs p{};
+    const double inv2h = 1.0 / (2.0 * g->d.hbar);
+    const int halves = (sa >= 0) + (sb >= 0);
+    p.aV = g->d.dt * inv2h * halves;
+    p.aA = g->d.charge * g->d.c * inv2h;
+    if (g->abar_steps > 0) {
+        if (sa >= 0) p.abar_a = g->abar_d + sa * g->n[0];
+        if (sb >= 0) p.abar_b = g->abar_d + sb * g->n[0];
+    }
+    p.ca = 1.0;
+    p.cb = 1.0;
+    p.sgn = sgn;
+    return p;
+}
+
+template <typename R> sfo_status dirac_xpass(sfo_grid g, void *psi, int64_t sa, int64_t sb, int sgn, int mode)
+{
+    const DiracPhaseArgs ph = dirac_phase_args(g, sa, sb, sgn);
+    HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
+        return launch_dirac_xpass<R>((int)g->n[0], (cx<R> *)psi, (int)g->n[1], g->ntot, g->V0, g->tw[0][0], ph, mode,
+                                     g->st);
+    }));
+    return SFO_OK;
+}
+
+template <typename R> sfo_status dirac_colpass(sfo_grid g, void *psi, int mode, int sgn)
+{
+    DiracKinArgs k{};
+    k.kx = g->kvec[0];
+    k.ky = g->kvec[1];
+    k.c = g->d.c;
+    k.mc2 = g->d.mass * g->d.c * g->d.c;
+    k.hbar = g->d.hbar;
+    k.tau_over_hbar = g->d.dt / g->d.hbar;
+    k.inv_ntot = 1.0 / (double)g->ntot;
+    k.sgn = sgn;
+    HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
+        return launch_dirac_colpass<R>((int)g->n[1], (cx<R> *)psi, (int)g->n[0], g->ntot, g->tw[1][0], k, mode, g->st);
+    }));
+    return SFO_OK;
+}
+
+template <typename R> sfo_status dirac_run(sfo_grid g, void *psi, int64_t step0, int64_t nsteps, int dir)
+{
+    if (nsteps == 0) return SFO_OK;
+    auto step_of = [&](int64_t s) { return dir > 0 ? step0 + s : step0 + nsteps - 1 - s; };
+    sfo_status s;
+    if (g->d.flags & SFO_UNFUSED) {
+        for (int64_t j = 0; j < nsteps; ++j) {
+            const int64_t st = step_of(j);
+            if ((s = dirac_xpass<R>(g, psi, -1, st, dir, M_PHASE))) return s;
+            if ((s = dirac_xpass<R>(g, psi, -1, -1, dir, M_FWD))) return s;
+            if ((s = dirac_colpass<R>(g, psi, M_FWD, dir))) return s;
+            if ((s = dirac_colpass<R>(g, psi, M_KIN, dir))) return s;
+            if ((s = dirac_colpass<R>(g, psi, M_INV, dir))) return s;
+            if ((s = dirac_xpass<R>(g, psi, -1, -1, dir, M_INV))) return s;
+            if ((s = dirac_xpass<R>(g, psi, st, -1, dir, M_PHASE))) return s;
+        }
+        return SFO_OK;
+    }
+    if ((s = dirac_xpass<R>(g, psi, -1, step_of(0), dir, M_PHASE | M_FWD))) return s;
+    for (int64_t j = 0; j < nsteps; ++j) {
+        if ((s = dirac_colpass<R>(g, psi, M_FWD | M_KIN | M_INV, dir))) return s;
+        const bool more = j + 1 < nsteps;
+        if ((s = dirac_xpass<R>(g, psi, step_of(j), more ? step_of(j + 1) : -1, dir,
+                                M_INV | M_PHASE | (more ? M_FWD : 0))))
+            return s;
+    }
+    return SFO_OK;
+}
+
 template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
 {
     const int mode = sign < 0 ? M_FWD : M_INV;
@@ -749,7 +823,8 @@ sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nstep
     if (!g || !psi_dev) return fail(SFO_E_INVALID, "null grid or state");
     sfo_status s = check_steps(g, step0, nsteps);
     if (s) return s;
-    if (g->d.equation == SFO_DIRAC) return fail(SFO_E_UNSUPPORTED, "Dirac propagation not built yet");
+    if (g->d.equation == SFO_DIRAC)
+        return g->c128 ? dirac_run<double>(g, psi_dev, step0, nsteps, +1) : dirac_run<float>(g, psi_dev, step0, nsteps, +1);
     return g->c128 ? schro_run<double>(g, psi_dev, step0, nsteps, +1) : schro_run<float>(g, psi_dev, step0, nsteps, +1);
 }
 
