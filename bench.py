@@ -14,7 +14,7 @@ the complex64 path (FP32 storage and butterflies, FP64 phases and
 reductions); the complex128 path, fused and in the paper's unfused
 five-launch form, is reported beside it.
 
-Prints ONE JSON line.  --gpus N with N > 1 is refused: this build runs on
+Prints ONE JSON line.  --gpus N with N > 1 is refused: the library runs on
 one GPU.
 """
 from __future__ import annotations
@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", choices=["c64", "c128", "all"], default="all")
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched control line")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 512 MiB device copy (the reference kernel for HBM counters)")
     return p.parse_args()
 
 
@@ -81,10 +84,79 @@ def bench_path(wl, dtype, flags, steps, warmup):
     kern = {name: g.profile_read(kind) for name, kind in
             (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
     g.profile(False)
+    fa = None
+    if dtype == "c64" and not flags:
+        # forward run + reverse sweep (state, adjoint and both gradients) of the same workload
+        gT = (0.5 * psi).contiguous()
+        g.propagate(psi, 0, wl.nsteps)
+        g.adjoint(psi, gT, 0, wl.nsteps)
+        reps = 2
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            g.propagate(psi, 0, wl.nsteps)
+            g.adjoint(psi, gT, 0, wl.nsteps)
+        torch.cuda.synchronize()
+        fa = (time.perf_counter() - ta) / reps
     g.close()
     del psi
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, plan=plan)
+    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, plan=plan, fwd_adj_seconds=fa)
+
+
+def bench_batch(reps=3):
+    """The 64-problem control batch (1-D 512..8192, 2-D 256^2..1024^2,
+    complex64, 400 steps): one batched forward call, and forward + reverse
+    sweep, timed over whole runs."""
+    import torch
+    from paper_1012_3911_amd import sfo, workloads as W
+
+    wls, targets, _ = W.control_batch()
+    S = wls[0].nsteps
+    grids = []
+    for wl in wls:
+        g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c64")
+        g.set_potential(wl.V0)
+        g.set_field(wl.ebar)
+        grids.append(g)
+    psis = [torch.from_numpy(wl.psi0).to("cuda").to(torch.complex64).contiguous() for wl in wls]
+    gs = [torch.from_numpy(t).to("cuda").to(torch.complex64).contiguous() for t in targets]
+    b = sfo.Batch(grids)
+    b.propagate(psis, 0, S)
+    b.adjoint(psis, gs, 0, S)
+    b.check()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.propagate(psis, 0, S)
+    b.check()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        b.propagate(psis, 0, S)
+        b.adjoint(psis, gs, 0, S)
+    b.check()
+    t2 = time.perf_counter()
+    pts = sum(wl.npoints for wl in wls)
+    b.close()
+    for g in grids:
+        g.close()
+    return {"problems": len(wls), "steps": S, "points": pts,
+            "fwd_ms_per_run": 1e3 * (t1 - t0) / reps, "fwd_updates_per_s": pts * S * reps / (t1 - t0),
+            "fwd_adjoint_ms_per_run": 1e3 * (t2 - t1) / reps,
+            "fwd_adjoint_updates_per_s": pts * S * reps / (t2 - t1)}
+
+
+def copy_calibration():
+    """A plain device copy of known size: the HBM counters of this kernel
+    calibrate FETCH_SIZE / WRITE_SIZE of the split-step kernels."""
+    import torch
+
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
 def cpu_baseline(wl, budget):
@@ -113,7 +185,7 @@ def cpu_baseline(wl, budget):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (got --gpus %d); multi-GPU sharding is not part of this build"
+        print("bench.py runs on one GPU only (got --gpus %d); the library has no multi-GPU sharding"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -122,6 +194,9 @@ def main():
     from paper_1012_3911_amd import sfo, workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
+        return
     wl = W.softcore_2d_laser(n=args.n)
     npts = wl.n[0] * wl.n[1]
     res = {}
@@ -193,6 +268,15 @@ def main():
                       "updates_per_s": npts * args.steps / v["seconds"], "plan": list(v["plan"])}
                   for k, v in res.items()},
     }
+    if r.get("fwd_adj_seconds"):
+        # each grid point is advanced once and walked back once per step
+        out["fwd_adjoint"] = {"updates_per_s": npts * wl.nsteps / r["fwd_adj_seconds"],
+                              "ms_per_step": 1e3 * r["fwd_adj_seconds"] / wl.nsteps,
+                              "note": "forward run + reverse sweep with dL/dEbar and dL/dV0, c64"}
+    if not args.no_batch:
+        out["batch"] = bench_batch()
+        print("# batch fwd %.2f ms/run, fwd+adjoint %.2f ms/run" % (out["batch"]["fwd_ms_per_run"],
+              out["batch"]["fwd_adjoint_ms_per_run"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

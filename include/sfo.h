@@ -48,11 +48,12 @@ extern "C" {
 #endif
 
 typedef struct sfo_grid_s *sfo_grid;
+typedef struct sfo_batch_s *sfo_batch;
 
 typedef enum {
     SFO_OK = 0,
     SFO_E_INVALID = -1,     /* bad argument: null pointer, size, index, table too short */
-    SFO_E_UNSUPPORTED = -2, /* valid request this build does not implement */
+    SFO_E_UNSUPPORTED = -2, /* valid request the library does not implement */
     SFO_E_NOMEM = -3,       /* device allocation failed */
     SFO_E_HIP = -4,         /* HIP runtime error (no device, launch failure) */
     SFO_E_STATE = -5        /* call out of order (e.g. no potential set) */
@@ -143,6 +144,43 @@ sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double 
  * exp(sign 2 pi i j m / N) along each axis, sign = -1 or +1 (the transform
  * the step uses internally; exposed for diagnostics). */
 sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign);
+
+/* Batched runs (Schroedinger, 1-D and 2-D).  Many independent problems of
+ * uneven size, each described by its own grid handle (its own box, time
+ * step, potential, field table and tile shapes), advance together: problems
+ * of one shape form a group, and each pass of the split step (Sec. 2.1, eq.
+ * step_t_to_t+dt_F) is launched once per group with the problem as a grid
+ * dimension, the 1-D whole runs on a parallel branch.  The launch sequence is
+ * captured once per (direction, step0, nsteps) in a HIP graph and replayed.
+ * The per-problem result equals sfo_propagate / sfo_adjoint on that grid
+ * to rounding (bit for bit when the grids of a shape share tile shapes).
+ *
+ * sfo_create_batch: `grids` (count >= 1, not owned, must outlive the batch)
+ * all of one dtype, Schroedinger, 1-D or 2-D (SFO_E_UNSUPPORTED otherwise).
+ * The batch launches on `hip_stream` (NULL = default stream), not on the
+ * grids' streams.  States are the caller's: psi_devs[i] (and g_devs[i]) are
+ * device pointers laid out as for grid i.  While a batched call is in
+ * flight, nothing else may touch these states or grids.
+ *
+ * sfo_propagate_batch: steps step0 .. step0+nsteps-1 of every problem.
+ * sfo_adjoint_batch: the reverse sweep of sfo_adjoint for every problem;
+ * dL_debar_devs[i] (nsteps x ndim) and dL_dV0_devs[i] (N points) are device
+ * pointers or NULL, and either array itself may be NULL.
+ * Both calls are asynchronous.  A changed list of state pointers (or a
+ * changed grid table) makes the call wait for the batch's earlier launches
+ * before it uploads the new problem descriptors.
+ *
+ * sfo_batch_set_graph: on = 0 launches the kernels directly instead of
+ * replaying graphs.
+ * sfo_batch_check: waits for the batch's stream; SFO_E_HIP if a launch
+ * failed. */
+sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stream, sfo_batch *out);
+sfo_status sfo_destroy_batch(sfo_batch b);
+sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0, int64_t nsteps);
+sfo_status sfo_adjoint_batch(sfo_batch b, void *const *psi_devs, void *const *g_devs, int64_t step0, int64_t nsteps,
+                             double *const *dL_debar_devs, double *const *dL_dV0_devs);
+sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on);
+sfo_status sfo_batch_check(sfo_batch b);
 
 /* Tile-shape planning.  Each line pass exists in several shapes (lines per
  * work-group, register radix, occupancy hint).  sfo_autotune times every

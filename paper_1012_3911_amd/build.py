@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfo.so")
-SOURCES = ["sfo_kernels.hip", "sfo_row.hip", "sfo_col.hip", "sfo_dirac.hip", "sfo_api.hip"]
+SOURCES = ["sfo_kernels.hip", "sfo_row.hip", "sfo_col.hip", "sfo_dirac.hip", "sfo_batch.hip", "sfo_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

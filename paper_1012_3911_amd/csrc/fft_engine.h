@@ -194,6 +194,46 @@ template <int NR, int DIR, typename R> __device__ __forceinline__ void dft(cx<R>
     }
 }
 
+#ifndef SFO_TW_GROUPED
+#define SFO_TW_GROUPED 1
+#endif
+
+// Stage twiddles and DFT of size NR = 8 or 16 in one pass: the twiddles of
+// the four inputs of each first-layer 4-point DFT are fetched and applied
+// just before it, so that at most four table entries are live at a time
+// instead of NR - 1 (for complex64 each entry is an FP32 hi/lo pair, four
+// registers).  Same arithmetic as twiddle() followed by dft<NR>().
+template <int NR, int DIR, typename R, typename TW>
+__device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int two, int L, int k)
+{
+    constexpr int N1 = 4, N2 = NR / 4;
+    cx<R> a[N2][N1];
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) {
+        // an opaque copy of the index pins this group's table loads here: the
+        // table is read-only, and the compiler would otherwise issue every
+        // load of the transform at its start and hold them all in registers
+        int kk = k;
+        __asm__ __volatile__("" : "+v"(kk));
+#pragma unroll
+        for (int j1 = 0; j1 < N1; ++j1) {
+            const int j = N2 * j1 + j2;
+            a[j2][j1] = j == 0 ? v[0] : twiddle<DIR>(v[j], tw, two + (j - 1) * L + kk);
+        }
+        dft<N1, DIR>(a[j2]);
+    }
+    twiddle_grid<NR, DIR, N1, N2>(a);
+#pragma unroll
+    for (int m1 = 0; m1 < N1; ++m1) {
+        cx<R> b[N2];
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) b[j2] = a[j2][m1];
+        dft<N2, DIR>(b);
+#pragma unroll
+        for (int m2 = 0; m2 < N2; ++m2) v[m1 + N1 * m2] = b[m2];
+    }
+}
+
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 // LDS placement of element p of a line during an exchange.  Bank conflicts
@@ -236,7 +276,8 @@ template <int N, int RAD> struct LineShape {
 // v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in
 // line; tw: the stage twiddle table of this (N, RAD).
 template <typename R, int N, int RAD, int DIR, int S, class MAP, int NV>
-__device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
+__device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                          bool act = true)
 {
     using Sh = LineShape<N, RAD>;
     static_assert(NV == Sh::RV, "register array size must match the line shape");
@@ -247,6 +288,9 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
     constexpr int r = Sh::radix(S), L = Sh::span(S), NB = RV / r;
     constexpr bool last = (S == Sh::NST - 1);
     constexpr int TWO = Sh::tw_offset(S);
+    // act = false: a thread beyond this line's T threads (a work-group sized for
+    // a longer line) keeps step with the barriers and touches nothing
+    if (act) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         cx<R> u[r];
@@ -254,11 +298,17 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         for (int j = 0; j < r; ++j) u[j] = v[i + j * NB];
         const int b = t + i * T;
         const int k = b & (L - 1);
-        if constexpr (L > 1) {
+        if constexpr (L > 1 && r >= 8 && SFO_TW_GROUPED) {
+            tw_dft<r, DIR>(u, tw, TWO, L, k);
+        } else {
+            if constexpr (L > 1) {
+                int kk = k;  // pins the table loads to this stage (see tw_dft)
+                __asm__ __volatile__("" : "+v"(kk));
 #pragma unroll
-            for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L + k);
+                for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L + kk);
+            }
+            dft<r, DIR>(u);
         }
-        dft<r, DIR>(u);
         if constexpr (last) {
 #pragma unroll
             for (int m = 0; m < r; ++m) v[i + m * NB] = u[m];
@@ -268,22 +318,40 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
             for (int m = 0; m < r; ++m) sh[MAP::at(base + m * L)] = u[m];
         }
     }
+    }
     if constexpr (!last) {
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[m] = sh[MAP::at(t + m * T)];
+            for (int m = 0; m < RV; ++m) v[m] = sh[MAP::at(t + m * T)];
+        }
         __syncthreads();
     }
 }
 
 // Full N-point transform of the thread's cyclic values (direction DIR), with
 // the LDS exchanges placed by MAP (RowMap<R, RAD> or ColMap<C>).
-template <typename R, int N, int RAD, int DIR, class MAP, int S = 0, int NV>
-__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw)
+template <typename R, int N, int RAD, int DIR, class MAP, int S, int NV>
+__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                         bool act, int)
 {
-    if constexpr (S < LineShape<N, RAD>::NST) {
-        fft_stage<R, N, RAD, DIR, S, MAP>(v, sh, t, tw);
-        fft_line<R, N, RAD, DIR, MAP, S + 1>(v, sh, t, tw);
+    if constexpr (S - 1 < LineShape<N, RAD>::NST) {
+        fft_stage<R, N, RAD, DIR, S - 1, MAP>(v, sh, t, tw, act);
+        fft_line<R, N, RAD, DIR, MAP, S + 1>(v, sh, t, tw, act, 0);
+    }
+}
+
+template <typename R, int N, int RAD, int DIR, class MAP, int S = 0, int NV>
+__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                         bool act = true)
+{
+    if constexpr (S == 0) {
+        // a fresh copy of the thread index per transform: the exchange
+        // addresses of two transforms in a row are then not shared (and kept
+        // live) between them
+        int tt = t;
+        __asm__ __volatile__("" : "+v"(tt));
+        fft_line<R, N, RAD, DIR, MAP, 1>(v, sh, tt, tw, act, 0);
     }
 }
 

@@ -11,6 +11,7 @@
 namespace sfo {
 
 template <typename R> using VStore = typename std::conditional<sizeof(R) == 4, float, double>::type;
+template <typename VT> __device__ __forceinline__ double ldv(const VT *p) { return (double)*p; }
 
 // sin and cos of |x| <= 1/8 by their Taylor series to x^11 / x^10
 // (truncation below 3e-20 relative); used for potential phases the host has
@@ -38,6 +39,55 @@ template <int N, int RAD, int THREADS> struct RowTile {
     static constexpr int NT = ROWS * Sh::T;
 };
 
+// Potential factor of a grouped row pass for problem P, covering the half
+// steps sa and sb (-1: absent); the same arguments the host forms for a
+// single grid (phase_args in sfo_api.hip).
+template <typename R>
+__device__ __forceinline__ PhaseArgs group_phase(const BatchProb<R> &P, int64_t sa, int64_t sb, int sgn)
+{
+    PhaseArgs ph{};
+    const int halves = (sa >= 0) + (sb >= 0);
+    ph.aV = P.aV_half * halves;
+    double bound = ph.aV * P.v0max;
+    for (int a = 0; a < 3; ++a) {
+        double e = 0.0;
+        if (a < P.ndim && P.ebar) {
+            if (sa >= 0) e += P.ebar[sa * P.ndim + a];
+            if (sb >= 0) e += P.ebar[sb * P.ndim + a];
+        }
+        ph.e[a] = e * P.inv_2hbar;
+        ph.xmin[a] = a < P.ndim ? P.xmin[a] : 0.0;
+        ph.dx[a] = a < P.ndim ? P.dx[a] : 0.0;
+        if (a < P.ndim) bound += fabs(ph.e[a]) * P.xabs[a];
+    }
+    ph.sgn = sgn;
+    ph.small = ph.aV * P.v0max <= 0.125 ? 1 : 0;
+    ph.small32 = bound <= 0.125 ? 1 : 0;
+    return ph;
+}
+
+// The arguments of a grouped row pass for this work-group's problem.
+template <typename R, int NS>
+__device__ __forceinline__ void group_row_args(const GroupArgs<R> &grp, StatePtrs<R> &S,
+                                               const VStore<R> *__restrict__ &V0, PhaseArgs &ph, GradArgs &ga)
+{
+    const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.y]];
+    S.p[0] = P.psi;
+    S.p[1] = NS == 2 ? P.gadj : nullptr;
+    V0 = P.V0;
+    ph = group_phase(P, grp.sa, grp.sb, ph.sgn);
+    if (NS == 2) {
+        ga.acc = P.dV;
+        ga.wacc = grp.wmul * P.aV_half;
+        ga.acc_init = grp.acc_init;
+        ga.part = P.part;
+        ga.count = P.count;
+        ga.mom = P.mom + 3 * grp.jmom;
+        ga.slot = (int)blockIdx.x;
+        ga.nslots = (int)gridDim.x;
+    }
+}
+
 // Sum of v over the work-group (all threads), FP64, deterministic order;
 // every thread returns the total.  red: 16 x 3 doubles of LDS.
 __device__ __forceinline__ void block_sum3(double (&v)[3], double (*red)[3])
@@ -58,24 +108,24 @@ __device__ __forceinline__ void block_sum3(double (&v)[3], double (*red)[3])
     __syncthreads();
 }
 
-// Work-group partial moments -> part[blockIdx.x]; the last group to finish
-// sums all partials in a fixed order into out[0..2] and re-arms the counter.
+// Work-group partial moments -> part[slot]; the last of the nslots groups to
+// finish sums all partials in a fixed order into out[0..2] and re-arms the
+// counter.
 __device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], double *part, unsigned *count,
-                                          double *out)
+                                          double *out, unsigned slot, unsigned nslots)
 {
     block_sum3(v, red);
     __shared__ unsigned last;
     if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) part[3 * blockIdx.x + a] = v[a];
+        for (int a = 0; a < 3; ++a) part[3 * slot + a] = v[a];
         __threadfence();
-        last = atomicAdd(count, 1u) == gridDim.x * gridDim.y - 1 ? 1u : 0u;
+        last = atomicAdd(count, 1u) == nslots - 1 ? 1u : 0u;
     }
     __syncthreads();
     if (last) {
         __threadfence();
-        const unsigned nb = gridDim.x * gridDim.y;
         double s[3] = {0.0, 0.0, 0.0};
-        for (unsigned i = threadIdx.x; i < nb; i += blockDim.x)
+        for (unsigned i = threadIdx.x; i < nslots; i += blockDim.x)
             for (int a = 0; a < 3; ++a) s[a] += __builtin_nontemporal_load(part + 3 * i + a);
         block_sum3(s, red);
         if (threadIdx.x == 0) {
@@ -83,6 +133,7 @@ __device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], doub
             *count = 0u;
         }
     }
+    __syncthreads();
 }
 
 // --------------------------------------------------------------- row pass --
@@ -97,31 +148,59 @@ __device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], doub
 // M_GRAD (NS = 2) additionally forms b = Im(conj(g) psi) at this step
 // boundary in real space: acc += w b (the dL/dV0 accumulator) and the
 // moments sum_x (x b, y b, z b) reduced over the grid into ga.mom.
-template <typename R, int N, int RAD, int THREADS, int WPE, int NS>
-__global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
-        PhaseArgs ph, GradArgs ga, int mode)
+template <typename R, int N, int RAD, int NS, int NV>
+__device__ __forceinline__ void row_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t row,
+                                         int t)
 {
-    using Sh = LineShape<N, RAD>;
-    constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, THREADS>::ROWS;
-    using Map = RowMap<R, RAD>;
-    __shared__ cx<R> lds[ROWS * Map::slots(N)];
-    __shared__ double red[16][3];
-    const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int64_t row = (int64_t)blockIdx.x * ROWS + line;
-    cx<R> *sh = lds + line * Map::slots(N);
-    cx<R> v[NS][RV];
-    VStore<R> vv[RV];
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][row * N + t + m * T];
-    if (mode & M_PHASE) {
-        // issue the potential loads now; they complete under the inverse transform
-        const VStore<R> *vr = V0 + row * N;
+}
+
+template <typename R, int N, int RAD, int NS, int NV>
+__device__ __forceinline__ void row_store(const cx<R> (&v)[NS][NV], const StatePtrs<R> &S,
+                                          int64_t row, int t)
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
 #pragma unroll
-        for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
-    }
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) S.p[q][row * N + t + m * T] = v[q][m];
+}
+
+template <typename R, int N, int RAD, int NV>
+__device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R> *__restrict__ V0,
+                                            int64_t row, int t)
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
+    const VStore<R> *vr = V0 + row * N;
+#pragma unroll
+    for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
+}
+
+// The register part of a row tile: inverse x-transform, potential factor,
+// gradient partials (mom accumulates this row's moments), forward
+// x-transform.  sh: this row's LDS exchange region; tw: twiddle table
+// (global or an LDS copy).
+template <typename R, int N, int RAD, int NS, int NV>
+__device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
+                                         const VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh,
+                                         int t, const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph,
+                                         const GradArgs &ga, int mode, double (&mom)[3])
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    // everything below is derived from an opaque copy of t: in a persistent
+    // loop the compiler would otherwise keep every tile-invariant value (16
+    // x coordinates, exchange addresses) live across all tiles
+    __asm__ __volatile__("" : "+v"(t));
+    using Sh = LineShape<N, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    using Map = RowMap<R, RAD>;
     if (mode & M_INV)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
@@ -137,7 +216,11 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
             const double x0 = ph.xmin[0] + (double)t * ph.dx[0], xs = (double)T * ph.dx[0];
 #pragma unroll
             for (int m = 0; m < RV; ++m) {
-                const double th = sg * (ph.aV * (double)vv[m] + ph.e[0] * (x0 + (double)m * xs) + base);
+                // the factor does not depend on psi; pinning its input here keeps
+                // the compiler from computing all of them during the transform
+                VStore<R> vm = vv[m];
+                __asm__ __volatile__("" : "+v"(vm));
+                const double th = sg * (ph.aV * (double)vm + ph.e[0] * (x0 + (double)m * xs) + base);
                 const float x = (float)th, x2 = x * x;
                 float ps = __builtin_fmaf(x2, -1.0f / 5040.0f, 1.0f / 120.0f);
                 ps = __builtin_fmaf(ps, x2, -1.0f / 6.0f);
@@ -161,25 +244,39 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
             sincos_fp64(sg * ph.e[0] * ((double)T * ph.dx[0]), s1, c1);
             double fr = c0, fi = -s0;  // exp(-i sg e.x) at x = t
             const double wr = c1, wi = -s1;
+            // one straight loop per series (the choice is uniform): a branch per
+            // point would split the loop into blocks and keep every value live
+            // across them
+            auto sweep = [&](auto sincos) {
 #pragma unroll
-            for (int m = 0; m < RV; ++m) {
-                const double th = sg * ph.aV * (double)vv[m];
-                double sv, cv;
-                if (ph.small) sincos_small(th, sv, cv);
-                else sincos_fp64(th, sv, cv);
-                // (cv - i sv) (fr + i fi)
-                const double tr = cv * fr + sv * fi, ti = cv * fi - sv * fr;
+                for (int m = 0; m < RV; ++m) {
+                    // pin this point's values here; the conversions to FP64 are
+                    // common to both loops and would otherwise all be hoisted
+                    // above the choice, holding 16 points in FP64 registers
 #pragma unroll
-                for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], tr, ti);
-                const double nr = fr * wr - fi * wi;
-                fi = fr * wi + fi * wr;
-                fr = nr;
-                if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the interleaving
-            }
+                    for (int q = 0; q < NS; ++q) __asm__ __volatile__("" : "+v"(v[q][m].re), "+v"(v[q][m].im));
+                    VStore<R> vm = vv[m];
+                    __asm__ __volatile__("" : "+v"(vm));
+                    const double th = sg * ph.aV * (double)vm;
+                    double sv, cv;
+                    sincos(th, sv, cv);
+                    // (cv - i sv) (fr + i fi)
+                    const double tr = cv * fr + sv * fi, ti = cv * fi - sv * fr;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], tr, ti);
+                    const double nr = fr * wr - fi * wi;
+                    fi = fr * wi + fi * wr;
+                    fr = nr;
+                    if ((m & 1) == 1) __builtin_amdgcn_sched_barrier(0);  // bound the interleaving
+                }
+            };
+            if (ph.small)
+                sweep([](double x, double &sn, double &cs) { sincos_small(x, sn, cs); });
+            else
+                sweep([](double x, double &sn, double &cs) { sincos_fp64(x, sn, cs); });
         }
     }
     if (NS == 2 && (mode & M_GRAD)) {
-        double mom[3] = {0.0, 0.0, 0.0};
         double sb = 0.0;
 #pragma unroll
         for (int m = 0; m < RV; ++m) {
@@ -193,17 +290,96 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
             sb += b;
             mom[0] += (ph.xmin[0] + (double)x * ph.dx[0]) * b;
         }
-        mom[1] = (ph.xmin[1] + (double)y * ph.dx[1]) * sb;
-        mom[2] = (ph.xmin[2] + (double)z * ph.dx[2]) * sb;
-        grid_sum3(mom, red, ga.part, ga.count, ga.mom);
+        mom[1] += (ph.xmin[1] + (double)y * ph.dx[1]) * sb;
+        mom[2] += (ph.xmin[2] + (double)z * ph.dx[2]) * sb;
     }
     if (mode & M_FWD)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+}
+
+template <typename R, int N, int RAD, int ROWS, int NS>
+__device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, int ny, const VStore<R> *__restrict__ V0,
+                                         const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
+                                         int mode, cx<R> *lds, double (*red)[3], int tid)
+{
+    using Sh = LineShape<N, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    const int line = tid / T, t = tid % T;
+    const int64_t row = row0 + line;
+    cx<R> *sh = lds + line * RowMap<R, RAD>::slots(N);
+    cx<R> v[NS][RV];
+    VStore<R> vv[RV];
+    row_load<R, N, RAD, NS>(v, S, row, t);
+    // the potential loads complete under the inverse transform
+    if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
+    double mom[3] = {0.0, 0.0, 0.0};
+    row_body<R, N, RAD, NS>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom);
+    row_store<R, N, RAD, NS>(v, S, row, t);
+    if (NS == 2 && (mode & M_GRAD)) {
+        const unsigned slot = ga.nslots ? (unsigned)ga.slot : blockIdx.x;
+        const unsigned nslots = ga.nslots ? (unsigned)ga.nslots : gridDim.x * gridDim.y;
+        grid_sum3(mom, red, ga.part, ga.count, ga.mom, slot, nslots);
+    }
+}
+
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS>
+__global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
+        PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
+{
+    constexpr int ROWS = RowTile<N, RAD, THREADS>::ROWS;
+    if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
+    __shared__ cx<R> lds[ROWS * RowMap<R, RAD>::slots(N)];
+    __shared__ double red[16][3];
+    row_tile<R, N, RAD, ROWS, NS>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red, threadIdx.x);
+}
+
+// Pipelined persistent row pass: work-group b takes tiles b, b + G, ...
+// (PIPE of them, G = gridDim.x).  The next tile's state is loaded into
+// registers while the current one is transformed, so its HBM traffic
+// overlaps arithmetic.  The twiddle table is staged in LDS once per group:
+// a vector-memory load issued inside the transform would have to wait for
+// the prefetch before it (loads complete in issue order).
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS, int PIPE>
+__global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_xpass_pipe(StatePtrs<R> S, int ny, int64_t ntiles, const VStore<R> *__restrict__ V0,
+             const TwEntry<R> *__restrict__ tw, PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
+{
+    if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
+    using Sh = LineShape<N, RAD>;
+    using Tl = RowTile<N, RAD, THREADS>;
+    constexpr int T = Sh::T, RV = Sh::RV, ROWS = Tl::ROWS;
+    constexpr int TWN = Sh::TW_SIZE > 0 ? Sh::TW_SIZE : 1;
+    __shared__ cx<R> lds[ROWS * RowMap<R, RAD>::slots(N)];
+    __shared__ TwEntry<R> twl[TWN];
+    __shared__ double red[16][3];
+    const int tid = threadIdx.x, line = tid / T, t = tid % T;
+    for (int i = tid; i < Sh::TW_SIZE; i += Tl::NT) twl[i] = tw[i];
+    cx<R> *sh = lds + line * RowMap<R, RAD>::slots(N);
+    const int64_t G = gridDim.x;
+    int64_t tile = blockIdx.x;
+    cx<R> v[NS][RV];
+    if (tile < ntiles) row_load<R, N, RAD, NS>(v, S, tile * ROWS + line, t);
+    __syncthreads();
+    double mom[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int i = 0; i < PIPE && tile < ntiles; ++i, tile += G) {
+        const int64_t row = tile * ROWS + line;
+        VStore<R> vv[RV];
+        if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
+        const bool more = i + 1 < PIPE && tile + G < ntiles;
+        cx<R> vn[NS][RV];
+        if (more) row_load<R, N, RAD, NS>(vn, S, (tile + G) * ROWS + line, t);
+        row_body<R, N, RAD, NS>(v, vv, row, ny, sh, t, twl, ph, ga, mode, mom);
+        row_store<R, N, RAD, NS>(v, S, row, t);
+        if (more)
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+            for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) S.p[q][row * N + t + m * T] = v[q][m];
+                for (int m = 0; m < RV; ++m) v[q][m] = vn[q][m];
+    }
+    if (NS == 2 && (mode & M_GRAD)) grid_sum3(mom, red, ga.part, ga.count, ga.mom, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------ column pass --
@@ -213,49 +389,244 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
 // Work-groups are dispatched round-robin over the 8 XCDs; the group index is
 // remapped so that consecutive column groups, which share cache lines, run
 // on the same XCD (and so share its L2) at about the same time.
-template <typename R, int N, int RAD, int C, int WPE, int NS>
-__global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw, KinArgs kin,
-          int mode)
+template <typename R, int N, int RAD, int NS, int NV>
+__device__ __forceinline__ void col_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t off,
+                                         int64_t stride, int t)
 {
-    using Sh = LineShape<N, RAD>;
-    constexpr int T = Sh::T, RV = Sh::RV;
-    using Map = ColMap<C>;
-    __shared__ cx<R> lds[Map::slots(N)];
-    const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const unsigned G = gridDim.x * gridDim.y;
-    unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
-    if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
-    const unsigned gx = L % gridDim.x, slab = L / gridDim.x;
-    const int64_t col = (int64_t)gx * C + c;
-    const int64_t off = (int64_t)slab * slab_stride + col;
-    cx<R> *sh = lds + c;
-    cx<R> v[NS][RV];
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][off + (int64_t)(t + m * T) * stride];
+}
+
+template <typename R, int N, int RAD, int NS, int NV>
+__device__ __forceinline__ void col_store(const cx<R> (&v)[NS][NV], const StatePtrs<R> &S,
+                                          int64_t off, int64_t stride, int t)
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    // strided addresses do not fit an immediate offset; recompute them here
+    // rather than holding the load addresses (two registers each) through
+    // the transforms
+    __asm__ __volatile__("" : "+v"(off), "+v"(t));
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) S.p[q][off + (int64_t)(t + m * T) * stride] = v[q][m];
+}
+
+// Forward transform, kinetic factor kc * kL[j] (kc: this line's factor from
+// the other axes), inverse transform.  kL: global table or an LDS copy.
+template <typename R, int N, int RAD, int C, int NS, int NV>
+__device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double kci, int sgn,
+                                         const double2 *kL, cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                         int mode)
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    __asm__ __volatile__("" : "+v"(t));  // see row_body
+    constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
+    using Map = ColMap<C>;
     if (mode & M_FWD)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
     if (mode & M_KIN) {
-        const double2 a = kin.kA[col % kin.nA], b = kin.kB[col / kin.nA];
-        const double kcr = a.x * b.x - a.y * b.y, kci = a.x * b.y + a.y * b.x;
+        // index laundered after the transform: the table loads stay here
+        // instead of being hoisted above it (16 FP64 pairs held through it)
+        int tk = t;
+        __asm__ __volatile__("" : "+v"(tk));
 #pragma unroll
         for (int m = 0; m < RV; ++m) {
-            const double2 l = kin.kL[t + m * T];
+            const double2 l = kL[tk + m * T];
             const double kr = kcr * l.x - kci * l.y, ki = kcr * l.y + kci * l.x;
 #pragma unroll
-            for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)kin.sgn * ki);
+            for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)sgn * ki);
+            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four points at a time
         }
     }
     if (mode & M_INV)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+}
+
+template <typename R, int N, int RAD, int C, int NS>
+__device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int64_t slab, int64_t stride,
+                                         int64_t slab_stride, const TwEntry<R> *__restrict__ tw, const KinArgs &kin,
+                                         int mode, cx<R> *lds, int tid)
+{
+    constexpr int RV = LineShape<N, RAD>::RV;
+    const int c = tid % C, t = tid / C;
+    const int64_t col = gx * C + c;
+    const int64_t off = slab * slab_stride + col;
+    cx<R> v[NS][RV];
+    col_load<R, N, RAD, NS>(v, S, off, stride, t);
+    double kcr = 1.0, kci = 0.0;
+    if (mode & M_KIN) {
+        const double2 a = kin.kA[col % kin.nA], b = kin.kB[col / kin.nA];
+        kcr = a.x * b.x - a.y * b.y;
+        kci = a.x * b.y + a.y * b.x;
+    }
+    col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode);
+    col_store<R, N, RAD, NS>(v, S, off, stride, t);
+}
+
+template <typename R, int N, int RAD, int C, int WPE, int NS>
+__global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw, KinArgs kin,
+          int mode, GroupArgs<R> grp)
+{
+    __shared__ cx<R> lds[ColMap<C>::slots(N)];
+    if (grp.probs) {
+        const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.z]];
+        S.p[0] = P.psi;
+        S.p[1] = NS == 2 ? P.gadj : nullptr;
+        kin.kA = P.kin_x;
+        kin.kB = P.one;
+        kin.kL = P.kin_y;
+        kin.nA = P.nx;
+    }
+    const unsigned G = gridDim.x * gridDim.y;
+    unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
+    if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
+    col_tile<R, N, RAD, C, NS>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds,
+                               threadIdx.x);
+}
+
+// ---------------------------------------------------------------- 1-D run --
+// One work-group per problem keeps its line in registers (cyclic layout) for
+// all steps; V0 of the thread's points is held in registers as well.  Steps
+// are visited forward (dir = +1) or backward with conjugated factors
+// (dir = -1, the exact inverse).  Consecutive half steps are merged:
+//   P_first, then per step: F, K, F^-1, P_s P_next (or P_s at the end).
+template <typename R, typename VT, int N, int RAD>
+__device__ __forceinline__ void run1d_tile(cx<R> *__restrict__ p, const VT *__restrict__ vp,
+                                           const TwEntry<R> *__restrict__ tw, const Run1DArgs &a, cx<R> *sh, int tid)
+{
+    using Sh = LineShape<N, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    // threads beyond T (a work-group sized for a longer line) only keep step with the barriers
+    const bool act = tid < T;
+    const int t = act ? tid : 0;
+    cx<R> v[RV];
+    if (act)
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+        for (int m = 0; m < RV; ++m) v[m] = p[t + m * T];
+    const double sg = (double)a.dir;
+    auto step_of = [&](int64_t s) { return a.dir > 0 ? a.step0 + s : a.step0 + a.nsteps - 1 - s; };
+    auto field = [&](int64_t st) { return a.ebar ? a.ebar[st] : 0.0; };
+    // V0, x and the kinetic table are re-read each step (L1/L2 hits) rather
+    // than held in registers, which keeps the line itself spill-free.
+    auto potential = [&](double av, double e) {
+        if (!act) return;
 #pragma unroll
-        for (int m = 0; m < RV; ++m) S.p[q][off + (int64_t)(t + m * T) * stride] = v[q][m];
+        for (int m = 0; m < RV; ++m) {
+            const int x = t + m * T;
+            v[m] = mul_expmi(v[m], sg * (av * ldv(vp + x) + e * (a.xmin + (double)x * a.dx)));
+            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the interleaving
+        }
+    };
+    if (a.nsteps > 0) potential(a.aV_half, field(step_of(0)) * a.inv_2hbar);
+#pragma unroll 1
+    for (int64_t s = 0; s < a.nsteps; ++s) {
+        // keep the table loads inside the loop: hoisting every twiddle, kinetic
+        // factor and potential value of all steps out of it exhausts registers
+        __asm__ __volatile__("" ::: "memory");
+        fft_line<R, N, RAD, -1, RowMap<R, RAD>>(v, sh, t, tw, act);
+        if (act)
+#pragma unroll
+            for (int m = 0; m < RV; ++m) {
+                const double2 k = a.kin[t + m * T];
+                v[m] = mul_phase(v[m], k.x, sg * k.y);
+            }
+        fft_line<R, N, RAD, +1, RowMap<R, RAD>>(v, sh, t, tw, act);
+        const bool more = s + 1 < a.nsteps;
+        potential(a.aV_half * (more ? 2.0 : 1.0),
+                  (field(step_of(s)) + (more ? field(step_of(s + 1)) : 0.0)) * a.inv_2hbar);
+    }
+    if (act)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) p[t + m * T] = v[m];
+}
+
+// Reverse sweep of a 1-D run: the state psi and its adjoint g are walked back
+// together with the exact inverse step (conjugated factors, last step first),
+// as run1d_tile does with dir = -1.  At every step boundary n (psi_n, g_n in
+// real space) it forms b_n = Im(conj(g_n) psi_n): the dL/dV0 accumulator
+// (registers) gains w_n b_n and mom[n] receives sum_x x b_n.
+template <typename R, typename VT, int N, int RAD>
+__device__ __forceinline__ void adj1d_tile(cx<R> *__restrict__ psi, cx<R> *__restrict__ gv,
+                                           const VT *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
+                                           const Run1DArgs &a, double wbase, double *acc_out, double *mom, cx<R> *sh,
+                                           double (*red)[3], int tid)
+{
+    using Sh = LineShape<N, RAD>;
+    using Map = RowMap<R, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    const bool act = tid < T;
+    const int t = act ? tid : 0;
+    cx<R> v[2][RV];
+    double acc[RV];
+#pragma unroll
+    for (int m = 0; m < RV; ++m) {
+        v[0][m] = act ? psi[t + m * T] : cx<R>{};
+        v[1][m] = act ? gv[t + m * T] : cx<R>{};
+        acc[m] = 0.0;
+    }
+    auto step_of = [&](int64_t s) { return a.step0 + a.nsteps - 1 - s; };
+    auto field = [&](int64_t st) { return a.ebar ? a.ebar[st] : 0.0; };
+    auto grad = [&](int64_t bidx, double w) {
+        double mo[3] = {0.0, 0.0, 0.0};
+        if (act)
+#pragma unroll
+            for (int m = 0; m < RV; ++m) {
+                const double b = (double)v[1][m].re * (double)v[0][m].im - (double)v[1][m].im * (double)v[0][m].re;
+                acc[m] += w * b;
+                mo[0] += (a.xmin + (double)(t + m * T) * a.dx) * b;
+            }
+        block_sum3(mo, red);
+        if (tid == 0)
+            for (int q = 0; q < 3; ++q) mom[3 * bidx + q] = mo[q];
+    };
+    auto potential = [&](double av, double e) {
+        if (!act) return;
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const int x = t + m * T;
+            const double th = -(av * (double)V0[x] + e * (a.xmin + (double)x * a.dx));
+            double sn, cs;
+            sincos_fp64(th, sn, cs);
+            v[0][m] = mul_phase(v[0][m], cs, -sn);
+            v[1][m] = mul_phase(v[1][m], cs, -sn);
+        }
+    };
+    grad(a.nsteps, wbase);
+    if (a.nsteps > 0) potential(a.aV_half, field(step_of(0)) * a.inv_2hbar);
+#pragma unroll 1
+    for (int64_t s = 0; s < a.nsteps; ++s) {
+        __asm__ __volatile__("" ::: "memory");
+        for (int q = 0; q < 2; ++q) {
+            fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw, act);
+            if (act)
+#pragma unroll
+                for (int m = 0; m < RV; ++m) {
+                    const double2 k = a.kin[t + m * T];
+                    v[q][m] = mul_phase(v[q][m], k.x, -k.y);
+                }
+            fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw, act);
+        }
+        const bool more = s + 1 < a.nsteps;
+        potential(a.aV_half * (more ? 2.0 : 1.0),
+                  (field(step_of(s)) + (more ? field(step_of(s + 1)) : 0.0)) * a.inv_2hbar);
+        grad(a.nsteps - 1 - s, (more ? 2.0 : 1.0) * wbase);
+    }
+    if (act)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            psi[t + m * T] = v[0][m];
+            gv[t + m * T] = v[1][m];
+            if (acc_out) acc_out[t + m * T] = acc[m];
+        }
 }
 
 // ------------------------------------------------------ variant dispatch --
@@ -264,12 +635,15 @@ template <typename R, int N, int V> constexpr bool row_variant_ok()
     constexpr RowVariant rv = kRowVariants[V];
     using Tl = RowTile<N, rv.rad, rv.threads>;
     if (N < 256 && V != 0) return false;  // short rows: default shape only
-    return Tl::NT <= 1024 && Tl::ROWS * RowMap<R, rv.rad>::slots(N) * (int)sizeof(cx<R>) <= 160 * 1024;
+    const int tw = rv.pipe > 1 ? LineShape<N, rv.rad>::TW_SIZE * (int)sizeof(TwEntry<R>) : 0;
+    // 1 KiB stays free for the reduction buffer and static LDS of the kernel
+    return Tl::NT <= 1024 && Tl::ROWS * RowMap<R, rv.rad>::slots(N) * (int)sizeof(cx<R>) + tw <= 159 * 1024;
 }
 
 template <typename R, int N, int V, int NS>
 hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0, const void *const *tws,
-                      const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st)
+                      const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st, const GroupArgs<R> &grp,
+                      int ngroup)
 {
     if constexpr (!row_variant_ok<R, N, V>()) {
         return hipErrorInvalidValue;
@@ -279,13 +653,19 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
         using Tl = RowTile<N, rv.rad, rv.threads>;
         if (nrows % Tl::ROWS) {
             // fewer rows than a work-group holds (a single 1-D line): one row per group
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS>), dim3((unsigned)nrows),
-                               dim3(LineShape<N, rv.rad>::T), 0, st, S, ny, (const VStore<R> *)V0,
-                               (const TwEntry<R> *)tw, ph, ga, mode);
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS>),
+                               dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), 0, st, S, ny,
+                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
+        } else if constexpr (rv.pipe > 1) {
+            const int64_t ntiles = nrows / Tl::ROWS;
+            const int64_t groups = (ntiles + rv.pipe - 1) / rv.pipe;
+            hipLaunchKernelGGL((k_xpass_pipe<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pipe>),
+                               dim3((unsigned)groups, (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny, ntiles,
+                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         } else {
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS>), dim3((unsigned)(nrows / Tl::ROWS)),
-                               dim3(Tl::NT), 0, st, S, ny, (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga,
-                               mode);
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS>),
+                               dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny,
+                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         }
         return hipGetLastError();
     }
@@ -294,10 +674,12 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
 template <typename R, int N, int NS, size_t... I>
 hipError_t row_dispatch(int var, const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0,
                         const void *const *tw, const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st,
-                        std::index_sequence<I...>)
+                        const GroupArgs<R> &grp, int ngroup, std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
-    ((var == (int)I ? (r = row_launch<R, N, (int)I, NS>(S, nrows, ny, V0, tw, ph, ga, mode, st), 0) : 0), ...);
+    ((var == (int)I ? (r = row_launch<R, N, (int)I, NS>(S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup), 0)
+                    : 0),
+     ...);
     return r;
 }
 
@@ -305,13 +687,13 @@ template <typename R, int N, int V> constexpr bool col_variant_ok()
 {
     constexpr ColVariant cv = kColVariants[V];
     if (N < 256 && V != 0) return false;
-    return cv.cols * LineShape<N, cv.rad>::T <= 1024 &&
-           ColMap<cv.cols>::slots(N) * (int)sizeof(cx<R>) <= 160 * 1024;
+    return cv.cols * LineShape<N, cv.rad>::T <= 1024 && ColMap<cv.cols>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024;
 }
 
 template <typename R, int N, int V, int NS>
 hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
-                      const void *const *tws, const KinArgs &kin, int mode, hipStream_t st)
+                      const void *const *tws, const KinArgs &kin, int mode, hipStream_t st, const GroupArgs<R> &grp,
+                      int ngroup)
 {
     if constexpr (!col_variant_ok<R, N, V>()) {
         return hipErrorInvalidValue;
@@ -320,8 +702,9 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
         const void *tw = tws[cv.rad == 8 ? 0 : 1];
         if (ncols % cv.cols) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>),
-                           dim3((unsigned)(ncols / cv.cols), (unsigned)nslab), dim3(cv.cols * LineShape<N, cv.rad>::T),
-                           0, st, S, stride, slab_stride, (const TwEntry<R> *)tw, kin, mode);
+                           dim3((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup),
+                           dim3(cv.cols * LineShape<N, cv.rad>::T), 0, st, S, stride, slab_stride,
+                           (const TwEntry<R> *)tw, kin, mode, grp);
         return hipGetLastError();
     }
 }
@@ -329,11 +712,13 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
 template <typename R, int N, int NS, size_t... I>
 hipError_t col_dispatch(int var, const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab,
                         int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st,
-                        std::index_sequence<I...>)
+                        const GroupArgs<R> &grp, int ngroup, std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
-    ((var == (int)I ? (r = col_launch<R, N, (int)I, NS>(S, ncols, stride, nslab, slab_stride, tw, kin, mode, st), 0)
-                    : 0),
+    ((var == (int)I
+          ? (r = col_launch<R, N, (int)I, NS>(S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup),
+             0)
+          : 0),
      ...);
     return r;
 }

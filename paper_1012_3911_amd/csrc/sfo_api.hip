@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "sfo.h"
+#include "sfo_batch.h"
 #include "sfo_impl.h"
 
 using namespace sfo;
@@ -61,7 +62,7 @@ struct sfo_grid_s {
     int row_var = 0;      // tile variants chosen for the x pass and the y/z passes
     int col_var[3] = {0, 0, 0};
     std::vector<double> ebar;  // host copy, nsteps x ndim
-    double *ebar_d = nullptr;  // device copy (1-D kernel reads it)
+    double *ebar_d = nullptr;  // device copy, nsteps x ndim (the 1-D and batched kernels read it)
     int64_t ebar_steps = 0;
     std::vector<double> abar;  // Dirac: nsteps x n[0]
     double *abar_d = nullptr;
@@ -685,6 +686,247 @@ template <typename R> sfo_status do_fft(sfo_grid g, void *psi, int sign)
 
 }  // namespace
 
+// ------------------------------------------------------------------ batch --
+// Problems are grouped by shape; a grouped launch covers one group (see
+// GroupArgs).  The launch sequence of a run is the single-grid one with every
+// pass launched once per group, captured once per (direction, step0, nsteps)
+// in a HIP graph and replayed on the caller's stream.
+struct sfo_batch_s {
+    std::vector<sfo_grid> grids;
+    bool c128 = false;
+    hipStream_t st = nullptr;    // the caller's stream: every launch or replay goes here
+    hipStream_t cap = nullptr;   // private streams the graphs are captured on
+    hipStream_t side = nullptr;  //   (1-D whole runs go on the side branch)
+    hipEvent_t fork = nullptr, join = nullptr;
+    struct Group {
+        int ndim, nx, ny;
+        int off, count;  // ids[off .. off+count)
+        sfo_grid rep;    // a grid of the group: its tables and tile shapes serve all
+    };
+    std::vector<Group> groups;
+    std::vector<int> ids;
+    int *ids_d = nullptr;
+    void *probs_d = nullptr;      // BatchProb<R>[count]
+    std::vector<char> probs_h;    // what probs_d holds
+    unsigned *counts = nullptr;   // per problem: reduction counter of the reverse sweep
+    double *work = nullptr;       // reverse sweep: moments and partials
+    int64_t work_cap = 0;
+    bool use_graph = true;
+    struct Graph {
+        int dir;
+        int64_t step0, nsteps;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+};
+
+namespace {
+
+void free_batch(sfo_batch b)
+{
+    if (!b) return;
+    for (auto &gr : b->graphs) (void)hipGraphExecDestroy(gr.exec);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    (void)hipFree(b->ids_d);
+    (void)hipFree(b->probs_d);
+    (void)hipFree(b->counts);
+    (void)hipFree(b->work);
+    delete b;
+}
+
+// Descriptors of every problem for one call; *work_need: the moment and
+// partial workspace of a reverse sweep (doubles).
+template <typename R>
+std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void *const *gadj, double *const *dE,
+                                      double *const *dV, int64_t nsteps, int64_t *work_need)
+{
+    const int n = (int)b->grids.size();
+    std::vector<BatchProb<R>> P(n);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const sfo_grid g = b->grids[i];
+        BatchProb<R> &q = P[i];
+        std::memset(&q, 0, sizeof q);
+        q.ndim = g->ndim;
+        q.nx = (int)g->n[0];
+        q.ny = (int)g->n[1];
+        q.psi = (cx<R> *)psi[i];
+        q.ebar = g->ebar_steps ? g->ebar_d : nullptr;
+        q.kin_x = g->kin[0];
+        q.kin_y = g->ndim > 1 ? g->kin[1] : nullptr;
+        q.one = g->one;
+        for (int a = 0; a < 3; ++a) {
+            q.xmin[a] = a < g->ndim ? g->d.xmin[a] : 0.0;
+            q.dx[a] = g->dx[a];
+            q.xabs[a] = a < g->ndim ? std::max(std::fabs(g->d.xmin[a]), std::fabs(g->d.xmax[a])) : 0.0;
+        }
+        q.aV_half = g->d.dt / (2.0 * g->d.hbar);
+        q.inv_2hbar = 1.0 / (2.0 * g->d.hbar);
+        q.v0max = g->v0max;
+        q.V0 = (decltype(q.V0))g->V0;
+        q.count = b->counts + i;
+        if (gadj) {
+            q.gadj = (cx<R> *)gadj[i];
+            q.dE = dE ? dE[i] : nullptr;
+            q.dV = dV ? dV[i] : nullptr;
+            q.mom = b->work ? b->work + off : nullptr;
+            off += 3 * (nsteps + 1);
+            q.part = b->work ? b->work + off : nullptr;
+            off += 3 * g->n[1];  // at least one slot per row work-group
+        }
+    }
+    *work_need = off;
+    return P;
+}
+
+// The launches of one batched run on stream s (1-D whole runs on `side`
+// when it is given, joined back before the end).
+template <typename R>
+hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hipStream_t s, hipStream_t side)
+{
+    const BatchProb<R> *pd = (const BatchProb<R> *)b->probs_d;
+    const int ns = dir < 0 ? 2 : 1;
+    const StatePtrs<R> none{{nullptr, nullptr}};
+    auto grp_of = [&](const sfo_batch_s::Group &G, int64_t sa, int64_t sb, int64_t jmom, double wmul, int init) {
+        GroupArgs<R> a{};
+        a.probs = pd;
+        a.ids = b->ids_d + G.off;
+        a.sa = sa;
+        a.sb = sb;
+        a.jmom = jmom;
+        a.wmul = wmul;
+        a.acc_init = init;
+        return a;
+    };
+    hipError_t e = hipSuccess;
+    if (dir < 0) e = launch_batch_reset(b->counts, (int)b->grids.size(), s);
+    // 1-D problems: one whole-run launch per length
+    hipStream_t s1 = side ? side : s;
+    if (e == hipSuccess && side) {
+        e = hipEventRecord(b->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, b->fork, 0);
+    }
+    for (const auto &G : b->groups) {
+        if (e != hipSuccess || G.ndim != 1) continue;
+        Run1DArgs a{};
+        a.step0 = step0;
+        a.nsteps = nsteps;
+        a.dir = dir;
+        const GroupArgs<R> grp = grp_of(G, -1, -1, 0, 1.0, 0);
+        e = dir > 0 ? launch_1d<R>(G.nx, nullptr, G.count, 0, nullptr, G.rep->tw[0][1], a, s1, grp)
+                    : launch_1d_adjoint<R>(G.nx, nullptr, nullptr, nullptr, G.rep->tw[0][1], a, 0.0, nullptr,
+                                           nullptr, s1, grp, G.count);
+    }
+    // 2-D problems: the fused single-grid sequence, each pass once per group
+    auto xpass = [&](int64_t sa, int64_t sb, int mode, int64_t jmom, double wmul, int init) {
+        for (const auto &G : b->groups) {
+            if (e != hipSuccess || G.ndim != 2) continue;
+            PhaseArgs ph{};
+            ph.sgn = dir;
+            e = launch_xpass<R>(G.rep->row_var, G.nx, ns, none, G.ny, G.ny, nullptr, (const void *const *)G.rep->tw[0],
+                                ph, GradArgs{}, mode, s, grp_of(G, sa, sb, jmom, wmul, init), G.count);
+        }
+    };
+    auto colpass = [&]() {
+        for (const auto &G : b->groups) {
+            if (e != hipSuccess || G.ndim != 2) continue;
+            KinArgs k{nullptr, nullptr, nullptr, 1, dir};
+            e = launch_colpass<R>(G.rep->col_var[1], G.ny, ns, none, G.nx, G.nx, 1, 0,
+                                  (const void *const *)G.rep->tw[1], k, M_FWD | M_KIN | M_INV, s,
+                                  grp_of(G, -1, -1, 0, 1.0, 0), G.count);
+        }
+    };
+    if (dir > 0) {
+        if (nsteps > 0) {
+            xpass(-1, step0, M_PHASE | M_FWD, 0, 1.0, 0);
+            for (int64_t j = 0; j < nsteps; ++j) {
+                colpass();
+                const bool more = j + 1 < nsteps;
+                xpass(step0 + j, more ? step0 + j + 1 : -1, M_INV | M_PHASE | (more ? M_FWD : 0), 0, 1.0, 0);
+            }
+        }
+    } else {
+        // reverse sweep (as schro_adjoint): boundary nsteps first, then each step backwards
+        xpass(-1, nsteps > 0 ? step0 + nsteps - 1 : -1, nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD, nsteps, 1.0,
+              1);
+        for (int64_t j = nsteps - 1; j >= 0; --j) {
+            colpass();
+            xpass(step0 + j, j > 0 ? step0 + j - 1 : -1, M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), j,
+                  j > 0 ? 2.0 : 1.0, 0);
+        }
+    }
+    if (e == hipSuccess && side) {
+        e = hipEventRecord(b->join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join, 0);
+    }
+    if (e == hipSuccess && dir < 0) e = launch_batch_ebar_grad<R>(pd, (int)b->grids.size(), nsteps, s);
+    return e;
+}
+
+template <typename R>
+sfo_status batch_run(sfo_batch b, void *const *psi, void *const *gadj, int64_t step0, int64_t nsteps, double *const *dE,
+                     double *const *dV)
+{
+    const int n = (int)b->grids.size();
+    const int dir = gadj ? -1 : +1;
+    for (int i = 0; i < n; ++i) {
+        if (!psi[i] || (gadj && !gadj[i])) return fail(SFO_E_INVALID, "problem %d: null state", i);
+        sfo_status s = check_steps(b->grids[i], step0, nsteps);
+        if (s) return fail(s, "problem %d: %s", i, g_err.c_str());
+    }
+    if (dir > 0 && nsteps == 0) return SFO_OK;
+    int64_t need = 0;
+    (void)batch_probs<R>(b, psi, gadj, dE, dV, nsteps, &need);
+    if (need > b->work_cap) {
+        HIP_TRY(hipStreamSynchronize(b->st));
+        (void)hipFree(b->work);
+        b->work = nullptr;
+        b->work_cap = 0;
+        HIP_TRY(hipMalloc(&b->work, sizeof(double) * need));
+        b->work_cap = need;
+    }
+    const std::vector<BatchProb<R>> P = batch_probs<R>(b, psi, gadj, dE, dV, nsteps, &need);
+    const size_t bytes = sizeof(BatchProb<R>) * P.size();
+    if (b->probs_h.size() != bytes || std::memcmp(b->probs_h.data(), P.data(), bytes) != 0) {
+        // earlier launches may still read the descriptors: let them finish first
+        HIP_TRY(hipStreamSynchronize(b->st));
+        HIP_TRY(hipMemcpy(b->probs_d, P.data(), bytes, hipMemcpyHostToDevice));
+        b->probs_h.assign((const char *)P.data(), (const char *)P.data() + bytes);
+    }
+    if (!b->use_graph) {
+        HIP_TRY(batch_enqueue<R>(b, dir, step0, nsteps, b->st, nullptr));
+        return SFO_OK;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &gr : b->graphs)
+        if (gr.dir == dir && gr.step0 == step0 && gr.nsteps == nsteps) exec = gr.exec;
+    if (!exec) {
+        if (b->graphs.size() >= 16) {
+            HIP_TRY(hipStreamSynchronize(b->st));
+            (void)hipGraphExecDestroy(b->graphs.front().exec);
+            b->graphs.erase(b->graphs.begin());
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        const hipError_t le = batch_enqueue<R>(b, dir, step0, nsteps, b->cap, b->side);
+        const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
+        if (le != hipSuccess && graph) (void)hipGraphDestroy(graph);
+        HIP_TRY(le);
+        HIP_TRY(ce);
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_TRY(ie);
+        b->graphs.push_back({dir, step0, nsteps, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, b->st));
+    return SFO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sfo_last_error(void) { return g_err.c_str(); }
@@ -792,11 +1034,9 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
     if (nsteps > 0) {
         for (double v : g->ebar)
             if (!std::isfinite(v)) return fail(SFO_E_INVALID, "field table holds a non-finite value");
-        // the 1-D kernel reads the x component of each step
-        std::vector<double> ex(nsteps);
-        for (int64_t s = 0; s < nsteps; ++s) ex[s] = g->ebar[s * g->ndim];
-        HIP_TRY(hipMalloc(&g->ebar_d, sizeof(double) * nsteps));
-        HIP_TRY(hipMemcpy(g->ebar_d, ex.data(), sizeof(double) * nsteps, hipMemcpyHostToDevice));
+        const size_t bytes = sizeof(double) * (size_t)nsteps * g->ndim;
+        HIP_TRY(hipMalloc(&g->ebar_d, bytes));
+        HIP_TRY(hipMemcpy(g->ebar_d, g->ebar.data(), bytes, hipMemcpyHostToDevice));
     }
     return SFO_OK;
 }
@@ -946,6 +1186,94 @@ sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *to
     }
     *count = (int64_t)g->ev[kind].size();
     *total_ms = sum;
+    return SFO_OK;
+}
+
+sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stream, sfo_batch *out)
+{
+    g_err.clear();
+    if (!grids || !out || count < 1) return fail(SFO_E_INVALID, "need an output handle and at least one grid");
+    *out = nullptr;
+    const bool c128 = grids[0] && grids[0]->c128;
+    for (int i = 0; i < count; ++i) {
+        const sfo_grid g = grids[i];
+        if (!g) return fail(SFO_E_INVALID, "grid %d is null", i);
+        if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "grid %d: batches hold Schroedinger grids", i);
+        if (g->c128 != c128) return fail(SFO_E_INVALID, "grid %d: every grid of a batch has the same dtype", i);
+        if (g->ndim > 2) return fail(SFO_E_UNSUPPORTED, "grid %d: batches hold 1-D and 2-D grids", i);
+    }
+    sfo_batch b = new sfo_batch_s;
+    b->grids.assign(grids, grids + count);
+    b->c128 = c128;
+    b->st = (hipStream_t)hip_stream;
+    // group by shape, in order of first appearance
+    for (int i = 0; i < count; ++i) {
+        const sfo_grid g = grids[i];
+        bool found = false;
+        for (const auto &G : b->groups)
+            found |= G.ndim == g->ndim && G.nx == (int)g->n[0] && G.ny == (int)g->n[1];
+        if (found) continue;
+        sfo_batch_s::Group G{g->ndim, (int)g->n[0], (int)g->n[1], (int)b->ids.size(), 0, g};
+        for (int k = i; k < count; ++k)
+            if (grids[k]->ndim == G.ndim && (int)grids[k]->n[0] == G.nx && (int)grids[k]->n[1] == G.ny) {
+                b->ids.push_back(k);
+                ++G.count;
+            }
+        b->groups.push_back(G);
+    }
+    auto guard = [&](hipError_t e) {
+        free_batch(b);
+        return fail(e == hipErrorOutOfMemory ? SFO_E_NOMEM : SFO_E_HIP, "batch set-up: %s", hipGetErrorString(e));
+    };
+    hipError_t e = hipStreamCreate(&b->cap);
+    if (e == hipSuccess) e = hipStreamCreate(&b->side);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&b->ids_d, sizeof(int) * b->ids.size());
+    if (e == hipSuccess) e = hipMemcpy(b->ids_d, b->ids.data(), sizeof(int) * b->ids.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->probs_d, (c128 ? sizeof(BatchProb<double>) : sizeof(BatchProb<float>)) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->counts, sizeof(unsigned) * count);
+    if (e == hipSuccess) e = hipMemset(b->counts, 0, sizeof(unsigned) * count);
+    if (e != hipSuccess) return guard(e);
+    *out = b;
+    return SFO_OK;
+}
+
+sfo_status sfo_destroy_batch(sfo_batch b)
+{
+    if (!b) return fail(SFO_E_INVALID, "null batch");
+    (void)hipStreamSynchronize(b->st);
+    free_batch(b);
+    return SFO_OK;
+}
+
+sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on)
+{
+    if (!b) return fail(SFO_E_INVALID, "null batch");
+    b->use_graph = on != 0;
+    return SFO_OK;
+}
+
+sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0, int64_t nsteps)
+{
+    if (!b || !psi_devs) return fail(SFO_E_INVALID, "null batch or state list");
+    return b->c128 ? batch_run<double>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr)
+                   : batch_run<float>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr);
+}
+
+sfo_status sfo_adjoint_batch(sfo_batch b, void *const *psi_devs, void *const *g_devs, int64_t step0, int64_t nsteps,
+                             double *const *dL_debar_devs, double *const *dL_dV0_devs)
+{
+    if (!b || !psi_devs || !g_devs) return fail(SFO_E_INVALID, "null batch, state list or adjoint list");
+    return b->c128 ? batch_run<double>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs)
+                   : batch_run<float>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs);
+}
+
+sfo_status sfo_batch_check(sfo_batch b)
+{
+    if (!b) return fail(SFO_E_INVALID, "null batch");
+    HIP_TRY(hipStreamSynchronize(b->st));
     return SFO_OK;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_engine.h"
 
 namespace sfo {
@@ -30,6 +32,8 @@ struct GradArgs {
     double *part;      // per-work-group partial moments, 3 per group
     unsigned *count;   // groups finished (0 on entry; the last group resets it)
     double *mom;       // out: sum_x (x, y, z) b over the grid
+    int slot, nslots;  // nslots > 0: this group's partial slot and the slot count
+                       // (persistent launches); 0: block index and grid size
 };
 
 // Real-space phase of a row pass: theta(x) = aV * V0(x) + e . x, applied as
@@ -86,37 +90,72 @@ struct Run1DArgs {
     int dir;          // +1 forward steps, -1 inverse steps (last first)
 };
 
+// One problem of a batch (device memory).  A grouped launch covers every
+// problem of one grid shape: the problem of a work-group is
+// probs[ids[slice]], slice = blockIdx.y (row passes), blockIdx.z (column
+// passes) or blockIdx.x (1-D whole runs).
+template <typename R> struct BatchProb {
+    int ndim, nx, ny;                  // 1-D: nx points; 2-D: nx x ny
+    cx<R> *psi;                        // state (caller's buffer)
+    cx<R> *gadj;                       // adjoint state (reverse sweep) or null
+    const double *ebar;                // per-step field integrals, ndim per step, or null
+    const double2 *kin_x, *kin_y;      // per-axis kinetic factors (1/N_tot in kin_x)
+    const double2 *one;                // {1, 0}
+    double xmin[3], dx[3], xabs[3];    // box; xabs = max |x| per axis
+    double aV_half, inv_2hbar, v0max;  // tau/(2 hbar), 1/(2 hbar), max |V0|
+    typename std::conditional<sizeof(R) == 4, const float, const double>::type *V0;
+    double *dV;                        // dL/dV0 (N points) or null
+    double *dE;                        // dL/dEbar (nsteps x ndim) or null
+    double *mom;                       // per boundary: sum_x (x, y, z) b, 3 (nsteps + 1)
+    double *part;                      // per row work-group partial moments
+    unsigned *count;                   // row work-groups finished in the current reduction
+};
+
+// Per-launch part of a grouped pass (probs == null: an ordinary launch).
+template <typename R> struct GroupArgs {
+    const BatchProb<R> *probs;
+    const int *ids;
+    int64_t sa, sb;   // row passes: half steps of the potential factor (-1: absent)
+    int64_t jmom;     // reverse sweep: step boundary of the gradient partials
+    double wmul;      // its weight (1 at the ends, 2 inside)
+    int acc_init;     // first boundary of the sweep: overwrite dL/dV0
+};
+
 // Tile shapes the planner chooses from (index = variant number).  Row
 // passes: register radix, threads per work-group (rows = threads / (N/radix)),
 // minimum waves per SIMD the register allocation must allow.  Column
 // passes: register radix, adjacent lines per work-group, waves per SIMD.
 struct RowVariant {
-    int rad, threads, wpe;
+    int rad, threads, wpe, pipe;  // pipe > 1: persistent, pipe tiles per group, prefetching
 };
 struct ColVariant {
     int rad, cols, wpe;
 };
-constexpr RowVariant kRowVariants[] = {{16, 256, 1}, {16, 128, 1}, {16, 512, 1}, {16, 256, 3},
-                                       {16, 256, 4}, {8, 256, 1},  {8, 512, 1},  {8, 256, 4}};
+constexpr RowVariant kRowVariants[] = {{16, 256, 1, 1}, {16, 128, 1, 1}, {16, 512, 1, 1}, {16, 256, 3, 1},
+                                       {16, 256, 4, 1}, {8, 256, 1, 1},  {8, 512, 1, 1},  {8, 256, 4, 1},
+                                       {16, 256, 1, 2}, {16, 512, 1, 2}, {16, 128, 1, 2}, {16, 256, 1, 4}};
 constexpr ColVariant kColVariants[] = {{16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2},
                                        {16, 2, 4}, {8, 8, 1},  {8, 4, 1},  {8, 2, 4}};
 constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);
 constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 
 // tw[0], tw[1]: the stage twiddle tables of the line length for radix 8 and 16.
+// grp / ngroup: a grouped launch over ngroup problems of the same shape
+// (S, V0, the phase and gradient arguments then come from the descriptors).
 template <typename R>
 hipError_t launch_xpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t nrows, int ny,
                         const void *V0, const void *const *tw, const PhaseArgs &ph, const GradArgs &ga,
-                        int mode, hipStream_t st);
+                        int mode, hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
 
 template <typename R>
 hipError_t launch_colpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t ncols, int64_t stride,
                           int nslab, int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode,
-                          hipStream_t st);
+                          hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
 
 template <typename R>
 hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a,
-                             double wbase, double *acc, double *mom, hipStream_t st);
+                             double wbase, double *acc, double *mom, hipStream_t st,
+                             const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
 
 // dL/dEbar[s][a] = (mom[s+1][a] + mom[s][a]) * scale for s < nsteps (mom: (nsteps+1) x 3).
 hipError_t launch_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out,
@@ -132,7 +171,7 @@ template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols)
 
 template <typename R>
 hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const void *V0,
-                     const void *tw, const Run1DArgs &a, hipStream_t st);
+                     const void *tw, const Run1DArgs &a, hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{});
 
 template <typename R>
 hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0,

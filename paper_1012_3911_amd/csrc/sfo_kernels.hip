@@ -14,137 +14,52 @@
 
 namespace sfo {
 
-template <typename VT> __device__ __forceinline__ double ldv(const VT *p) { return (double)*p; }
 
 // ---------------------------------------------------------------- 1-D run --
-// One work-group per problem keeps its line in registers (cyclic layout) for
-// all steps; V0 of the thread's points is held in registers as well.  Steps
-// are visited forward (dir = +1) or backward with conjugated factors
-// (dir = -1, the exact inverse).  Consecutive half steps are merged:
-//   P_first, then per step: F, K, F^-1, P_s P_next (or P_s at the end).
+// 1-D whole-run arguments of problem P of a grouped launch.
+template <typename R> __device__ __forceinline__ void group_1d_args(const BatchProb<R> &P, Run1DArgs &a)
+{
+    a.kin = P.kin_x;
+    a.ebar = P.ebar;
+    a.aV_half = P.aV_half;
+    a.inv_2hbar = P.inv_2hbar;
+    a.xmin = P.xmin[0];
+    a.dx = P.dx[0];
+}
+
 template <typename R, typename VT, int N, int RAD>
 __global__ void __launch_bounds__((LineShape<N, RAD>::T))
     k_1d_run(cx<R> *__restrict__ psi, int64_t prob_stride, const VT *__restrict__ V0,
-             const TwEntry<R> *__restrict__ tw, Run1DArgs a)
+             const TwEntry<R> *__restrict__ tw, Run1DArgs a, GroupArgs<R> grp)
 {
-    using Sh = LineShape<N, RAD>;
-    constexpr int T = Sh::T, RV = Sh::RV;
     __shared__ cx<R> sh[RowMap<R, RAD>::slots(N)];
-    const int t = threadIdx.x;
-    cx<R> *p = psi + (int64_t)blockIdx.x * prob_stride;
-    const VT *vp = V0 + (int64_t)blockIdx.x * prob_stride;
-    cx<R> v[RV];
-#pragma unroll
-    for (int m = 0; m < RV; ++m) v[m] = p[t + m * T];
-    const double sg = (double)a.dir;
-    auto step_of = [&](int64_t s) { return a.dir > 0 ? a.step0 + s : a.step0 + a.nsteps - 1 - s; };
-    auto field = [&](int64_t st) { return a.ebar ? a.ebar[st] : 0.0; };
-    // V0, x and the kinetic table are re-read each step (L1/L2 hits) rather
-    // than held in registers, which keeps the line itself spill-free.
-    auto potential = [&](double av, double e) {
-#pragma unroll
-        for (int m = 0; m < RV; ++m) {
-            const int x = t + m * T;
-            v[m] = mul_expmi(v[m], sg * (av * ldv(vp + x) + e * (a.xmin + (double)x * a.dx)));
-            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the interleaving
-        }
-    };
-    if (a.nsteps > 0) potential(a.aV_half, field(step_of(0)) * a.inv_2hbar);
-#pragma unroll 1
-    for (int64_t s = 0; s < a.nsteps; ++s) {
-        // keep the table loads inside the loop: hoisting every twiddle, kinetic
-        // factor and potential value of all steps out of it exhausts registers
-        __asm__ __volatile__("" ::: "memory");
-        fft_line<R, N, RAD, -1, RowMap<R, RAD>>(v, sh, t, tw);
-#pragma unroll
-        for (int m = 0; m < RV; ++m) {
-            const double2 k = a.kin[t + m * T];
-            v[m] = mul_phase(v[m], k.x, sg * k.y);
-        }
-        fft_line<R, N, RAD, +1, RowMap<R, RAD>>(v, sh, t, tw);
-        const bool more = s + 1 < a.nsteps;
-        potential(a.aV_half * (more ? 2.0 : 1.0),
-                  (field(step_of(s)) + (more ? field(step_of(s + 1)) : 0.0)) * a.inv_2hbar);
+    if (grp.probs) {
+        const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.x]];
+        group_1d_args(P, a);
+        run1d_tile<R, VT, N, RAD>(P.psi, (const VT *)P.V0, tw, a, sh, threadIdx.x);
+        return;
     }
-#pragma unroll
-    for (int m = 0; m < RV; ++m) p[t + m * T] = v[m];
+    run1d_tile<R, VT, N, RAD>(psi + (int64_t)blockIdx.x * prob_stride, V0 + (int64_t)blockIdx.x * prob_stride, tw, a,
+                              sh, threadIdx.x);
 }
 
 // ------------------------------------------------------------ 1-D adjoint --
-// Reverse sweep of a 1-D run: the state psi and its adjoint g are walked back
-// together with the exact inverse step (conjugated factors, last step first),
-// as the forward whole-run kernel does with dir = -1.  At every step boundary
-// n (psi_n, g_n in real space) it forms b_n = Im(conj(g_n) psi_n): the dL/dV0
-// accumulator (registers) gains w_n b_n and mom[n] receives sum_x x b_n.
 template <typename R, typename VT, int N, int RAD>
 __global__ void __launch_bounds__((LineShape<N, RAD>::T))
     k_1d_adjoint(cx<R> *__restrict__ psi, cx<R> *__restrict__ gv, const VT *__restrict__ V0,
-                 const TwEntry<R> *__restrict__ tw, Run1DArgs a, double wbase, double *acc_out, double *mom)
+                 const TwEntry<R> *__restrict__ tw, Run1DArgs a, double wbase, double *acc_out, double *mom,
+                 GroupArgs<R> grp)
 {
-    using Sh = LineShape<N, RAD>;
-    using Map = RowMap<R, RAD>;
-    constexpr int T = Sh::T, RV = Sh::RV;
-    __shared__ cx<R> sh[Map::slots(N)];
+    __shared__ cx<R> sh[RowMap<R, RAD>::slots(N)];
     __shared__ double red[16][3];
-    const int t = threadIdx.x;
-    cx<R> v[2][RV];
-    double acc[RV];
-#pragma unroll
-    for (int m = 0; m < RV; ++m) {
-        v[0][m] = psi[t + m * T];
-        v[1][m] = gv[t + m * T];
-        acc[m] = 0.0;
+    if (grp.probs) {
+        const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.x]];
+        group_1d_args(P, a);
+        adj1d_tile<R, VT, N, RAD>(P.psi, P.gadj, (const VT *)P.V0, tw, a, P.aV_half, P.dV, P.mom, sh, red,
+                                  threadIdx.x);
+        return;
     }
-    auto step_of = [&](int64_t s) { return a.step0 + a.nsteps - 1 - s; };
-    auto field = [&](int64_t st) { return a.ebar ? a.ebar[st] : 0.0; };
-    auto grad = [&](int64_t bidx, double w) {
-        double mo[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int m = 0; m < RV; ++m) {
-            const double b = (double)v[1][m].re * (double)v[0][m].im - (double)v[1][m].im * (double)v[0][m].re;
-            acc[m] += w * b;
-            mo[0] += (a.xmin + (double)(t + m * T) * a.dx) * b;
-        }
-        block_sum3(mo, red);
-        if (t == 0)
-            for (int q = 0; q < 3; ++q) mom[3 * bidx + q] = mo[q];
-    };
-    auto potential = [&](double av, double e) {
-#pragma unroll
-        for (int m = 0; m < RV; ++m) {
-            const int x = t + m * T;
-            const double th = -(av * (double)V0[x] + e * (a.xmin + (double)x * a.dx));
-            double sn, cs;
-            sincos_fp64(th, sn, cs);
-            v[0][m] = mul_phase(v[0][m], cs, -sn);
-            v[1][m] = mul_phase(v[1][m], cs, -sn);
-        }
-    };
-    grad(a.nsteps, wbase);
-    if (a.nsteps > 0) potential(a.aV_half, field(step_of(0)) * a.inv_2hbar);
-#pragma unroll 1
-    for (int64_t s = 0; s < a.nsteps; ++s) {
-        __asm__ __volatile__("" ::: "memory");
-        for (int q = 0; q < 2; ++q) {
-            fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
-#pragma unroll
-            for (int m = 0; m < RV; ++m) {
-                const double2 k = a.kin[t + m * T];
-                v[q][m] = mul_phase(v[q][m], k.x, -k.y);
-            }
-            fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
-        }
-        const bool more = s + 1 < a.nsteps;
-        potential(a.aV_half * (more ? 2.0 : 1.0),
-                  (field(step_of(s)) + (more ? field(step_of(s + 1)) : 0.0)) * a.inv_2hbar);
-        grad(a.nsteps - 1 - s, (more ? 2.0 : 1.0) * wbase);
-    }
-#pragma unroll
-    for (int m = 0; m < RV; ++m) {
-        psi[t + m * T] = v[0][m];
-        gv[t + m * T] = v[1][m];
-        if (acc_out) acc_out[t + m * T] = acc[m];
-    }
+    adj1d_tile<R, VT, N, RAD>(psi, gv, V0, tw, a, wbase, acc_out, mom, sh, red, threadIdx.x);
 }
 
 __global__ void k_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out)
@@ -293,40 +208,41 @@ constexpr int kRad = 16;
 
 template <typename R, typename VT, int N>
 static hipError_t run1d_n(cx<R> *psi, int nprob, int64_t prob_stride, const void *V0, const void *tw,
-                          const Run1DArgs &a, hipStream_t st)
+                          const Run1DArgs &a, hipStream_t st, const GroupArgs<R> &grp)
 {
     constexpr int threads = LineShape<N, kRad>::T;
     hipLaunchKernelGGL((k_1d_run<R, VT, N, kRad>), dim3((unsigned)nprob), dim3(threads), 0, st, psi, prob_stride,
-                       (const VT *)V0, (const TwEntry<R> *)tw, a);
+                       (const VT *)V0, (const TwEntry<R> *)tw, a, grp);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const void *V0, const void *tw,
-                     const Run1DArgs &a, hipStream_t st)
+                     const Run1DArgs &a, hipStream_t st, const GroupArgs<R> &grp)
 {
     using VT = typename std::conditional<sizeof(R) == 4, float, double>::type;
-#define CALL(n) run1d_n<R, VT, n>(psi, nprob, prob_stride, V0, tw, a, st)
+#define CALL(n) run1d_n<R, VT, n>(psi, nprob, prob_stride, V0, tw, a, st, grp)
     SFO_SWITCH_1D_N(N, CALL)
 #undef CALL
 }
 
 template <typename R, typename VT, int N>
 static hipError_t adj1d_n(cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a, double wbase,
-                          double *acc, double *mom, hipStream_t st)
+                          double *acc, double *mom, hipStream_t st, const GroupArgs<R> &grp, int ngroup)
 {
     constexpr int threads = LineShape<N, kRad>::T;
-    hipLaunchKernelGGL((k_1d_adjoint<R, VT, N, kRad>), dim3(1), dim3(threads), 0, st, psi, gv, (const VT *)V0,
-                       (const TwEntry<R> *)tw, a, wbase, acc, mom);
+    hipLaunchKernelGGL((k_1d_adjoint<R, VT, N, kRad>), dim3((unsigned)ngroup), dim3(threads), 0, st, psi, gv,
+                       (const VT *)V0, (const TwEntry<R> *)tw, a, wbase, acc, mom, grp);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a,
-                             double wbase, double *acc, double *mom, hipStream_t st)
+                             double wbase, double *acc, double *mom, hipStream_t st, const GroupArgs<R> &grp,
+                             int ngroup)
 {
     using VT = typename std::conditional<sizeof(R) == 4, float, double>::type;
-#define CALL(n) adj1d_n<R, VT, n>(psi, gv, V0, tw, a, wbase, acc, mom, st)
+#define CALL(n) adj1d_n<R, VT, n>(psi, gv, V0, tw, a, wbase, acc, mom, st, grp, ngroup)
     SFO_SWITCH_1D_N(N, CALL)
 #undef CALL
 }
@@ -370,13 +286,15 @@ hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t
 }
 
 template hipError_t launch_1d<float>(int, cx<float> *, int, int64_t, const void *, const void *, const Run1DArgs &,
-                                     hipStream_t);
+                                     hipStream_t, const GroupArgs<float> &);
 template hipError_t launch_1d<double>(int, cx<double> *, int, int64_t, const void *, const void *, const Run1DArgs &,
-                                      hipStream_t);
+                                      hipStream_t, const GroupArgs<double> &);
 template hipError_t launch_1d_adjoint<float>(int, cx<float> *, cx<float> *, const void *, const void *,
-                                             const Run1DArgs &, double, double *, double *, hipStream_t);
+                                             const Run1DArgs &, double, double *, double *, hipStream_t,
+                                             const GroupArgs<float> &, int);
 template hipError_t launch_1d_adjoint<double>(int, cx<double> *, cx<double> *, const void *, const void *,
-                                              const Run1DArgs &, double, double *, double *, hipStream_t);
+                                              const Run1DArgs &, double, double *, double *, hipStream_t,
+                                              const GroupArgs<double> &, int);
 template hipError_t launch_norm<float>(const cx<float> *, int64_t, double *, double *, hipStream_t);
 template hipError_t launch_norm<double>(const cx<double> *, int64_t, double *, double *, hipStream_t);
 template hipError_t launch_overlap<float>(const cx<float> *, const cx<float> *, int64_t, double *, double *,

@@ -52,8 +52,9 @@ _lib = None
 
 EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_field",
            "sfo_set_vector_potential", "sfo_step", "sfo_propagate", "sfo_adjoint", "sfo_norm",
-           "sfo_overlap", "sfo_fft", "sfo_autotune", "sfo_get_plan", "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_last_error",
-           "sfo_version"]
+           "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
+           "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
+           "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_last_error", "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 
@@ -84,6 +85,12 @@ def load_library(path: str = LIB_PATH):
         "sfo_set_plan": [P, P],
         "sfo_profile_enable": [P, I32],
         "sfo_profile_read": [P, I32, P, P],
+        "sfo_create_batch": [P, I32, P, ctypes.POINTER(P)],
+        "sfo_destroy_batch": [P],
+        "sfo_propagate_batch": [P, P, I64, I64],
+        "sfo_adjoint_batch": [P, P, P, I64, I64, P, P],
+        "sfo_batch_set_graph": [P, I32],
+        "sfo_batch_check": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -245,6 +252,69 @@ class Grid:
 
     def fft(self, psi, sign: int = -1):
         _check(_lib.sfo_fft(self._h, self._state(psi), int(sign)), "sfo_fft")
+
+
+class Batch:
+    """Many independent Schroedinger grids (1-D and 2-D) advanced together.
+
+    The grids (all of one dtype) keep their own box, time step, potential and
+    field table.  Each pass is launched once per group of same-shape grids;
+    the batch runs on one stream (torch's current stream by default) and
+    replays a captured HIP graph per (direction, step0, nsteps).
+    """
+
+    def __init__(self, grids: Sequence[Grid], stream=None, graph: bool = True):
+        torch = _torch()
+        lib = load_library()
+        if not grids:
+            raise ValueError("a batch needs at least one grid")
+        self.grids = list(grids)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (ctypes.c_void_p * len(grids))(*[g._h.value for g in grids])
+        h = ctypes.c_void_p()
+        _check(lib.sfo_create_batch(arr, len(grids), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "sfo_create_batch")
+        self._h = h
+        if not graph:
+            _check(lib.sfo_batch_set_graph(self._h, 0), "sfo_batch_set_graph")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(_lib.sfo_destroy_batch(self._h), "sfo_destroy_batch")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, states, name):
+        if len(states) != len(self.grids):
+            raise ValueError("%s: need %d states, got %d" % (name, len(self.grids), len(states)))
+        return (ctypes.c_void_p * len(states))(*[g._state(x, name).value for g, x in zip(self.grids, states)])
+
+    def set_graph(self, on: bool):
+        _check(_lib.sfo_batch_set_graph(self._h, 1 if on else 0), "sfo_batch_set_graph")
+
+    def propagate(self, psis, step0: int, nsteps: int):
+        _check(_lib.sfo_propagate_batch(self._h, self._ptrs(psis, "psi"), int(step0), int(nsteps)),
+               "sfo_propagate_batch")
+
+    def adjoint(self, psis, gs, step0: int, nsteps: int, want_dV0: bool = True):
+        """Reverse sweep of every problem; returns (list of dL/dEbar, list of dL/dV0 or None)."""
+        torch = _torch()
+        des = [torch.zeros((nsteps, g.ndim), dtype=torch.float64, device="cuda") for g in self.grids]
+        dvs = [torch.zeros(g.n[::-1], dtype=torch.float64, device="cuda") for g in self.grids] if want_dV0 else None
+        de_arr = (ctypes.c_void_p * len(des))(*[d.data_ptr() for d in des])
+        dv_arr = (ctypes.c_void_p * len(dvs))(*[d.data_ptr() for d in dvs]) if dvs is not None else None
+        _check(_lib.sfo_adjoint_batch(self._h, self._ptrs(psis, "psi"), self._ptrs(gs, "g"), int(step0),
+                                      int(nsteps), de_arr, dv_arr), "sfo_adjoint_batch")
+        return des, dvs
+
+    def check(self):
+        """Wait for the batch's stream; raise if a launch gave up on a dependency."""
+        _check(_lib.sfo_batch_check(self._h), "sfo_batch_check")
 
 
 def version() -> str:

@@ -78,4 +78,10 @@ def test_null_arguments(lib):
     assert lib.sfo_destroy_grid(None) == -1
     assert lib.sfo_propagate(None, None, 0, 1) == -1
     assert lib.sfo_norm(None, None, None) == -1
+    assert lib.sfo_create_batch(None, 0, None, ctypes.byref(h)) == -1
+    assert lib.sfo_destroy_batch(None) == -1
+    assert lib.sfo_propagate_batch(None, None, 0, 1) == -1
+    assert lib.sfo_adjoint_batch(None, None, None, 0, 1, None, None) == -1
+    assert lib.sfo_batch_set_graph(None, 1) == -1
+    assert lib.sfo_batch_check(None) == -1
     assert lib.sfo_version().decode().startswith("sfo")

@@ -1,0 +1,253 @@
+"""Batched runs (grouped launches under a HIP graph) against the oracle.
+
+Every problem of a batch (uneven 1-D and 2-D sizes, each with its own box,
+time step, potential and field table) must match the FP64 oracle run of that
+problem alone, forward and in the reverse sweep, to the single-grid
+tolerances: complex128 1e-12 relative L2 (forward) / 1e-10 (gradients),
+complex64 1e-5 (forward) / 1e-4 (gradients).  HIP graph replays must
+reproduce the directly launched result bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_1012_3911_amd import workloads as W
+from gpu_util import make_grid, oracle_run, rel_l2, to_device
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = {"c128": 1e-12, "c64": 1e-5}
+GRAD_TOL = {"c128": 1e-10, "c64": 1e-4}
+
+
+def mixed_problems(seed=11, nsteps=40):
+    """Uneven sizes, one problem per shape: 1-D 256 .. 8192 points, 2-D square
+    and rectangular grids of 128 .. 1024 points per axis."""
+    rng = np.random.default_rng(seed)
+    shapes = [(256,), (8192,), (1024,), (128, 128), (256, 128), (128, 512), (1024, 128), (512, 256)]
+    out = []
+    for i, n in enumerate(shapes):
+        nd = len(n)
+        half = rng.uniform(8.0, 30.0, size=nd)
+        lo, hi = tuple(-h for h in half), tuple(half)
+        X = W.mesh(n, lo, hi) if nd > 1 else W.axes(n, lo, hi)
+        r2 = sum(x**2 for x in X)
+        V0 = -rng.uniform(0.5, 2.0) / np.sqrt(r2 + rng.uniform(0.5, 2.0))
+        k0 = tuple(rng.uniform(-1.0, 1.0, size=nd))
+        psi0 = W.gaussian(n, lo, hi, (0.0,) * nd, 1.0, k0)
+        dt = float(rng.uniform(0.01, 0.05))
+        ebar = dt * rng.uniform(-0.2, 0.2, size=(nsteps, nd))
+        out.append(W.Workload("mix%d" % i, "schrodinger", n, lo, hi, dt, nsteps, V0, psi0, ebar=ebar))
+    return out
+
+
+def run_batch(wls, dtype, step0, nsteps, graph=True):
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    grids = [make_grid(wl, dtype) for wl in wls]
+    psis = [to_device(wl.psi0, dtype) for wl in wls]
+    b = sfo.Batch(grids, graph=graph)
+    b.propagate(psis, step0, nsteps)
+    b.check()
+    torch.cuda.synchronize()
+    out = [p.cpu().numpy().astype(np.complex128) for p in psis]
+    b.close()
+    for g in grids:
+        g.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_forward_matches_oracle(orc, dtype):
+    wls = mixed_problems()
+    step0, ns = 5, 30
+    got = run_batch(wls, dtype, step0, ns)
+    for wl, g in zip(wls, got):
+        ref = oracle_run(orc, wl, nsteps=ns, step0=step0)
+        err = rel_l2(g, ref)
+        print("%-6s %-12s rel L2 %.2e" % (dtype, wl.n, err), flush=True)
+        assert err < FWD_TOL[dtype], (wl.n, err)
+
+
+def test_batch_single_problem_and_zero_steps(orc):
+    wls = mixed_problems()[3:4]
+    got = run_batch(wls, "c128", 0, 0)
+    assert np.array_equal(got[0], wls[0].psi0.astype(np.complex128))
+    got = run_batch(wls, "c128", 0, 1)
+    assert rel_l2(got[0], oracle_run(orc, wls[0], nsteps=1)) < 1e-13
+
+
+def test_batch_graph_replays_match_direct_launch():
+    """A captured graph, replayed several times with other work and
+    synchronisations in between, gives the directly launched result exactly."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls = mixed_problems()
+    direct = run_batch(wls, "c64", 0, 20, graph=False)
+    grids = [make_grid(wl, "c64") for wl in wls]
+    b = sfo.Batch(grids, graph=True)
+    other = to_device(wls[3].psi0, "c64")
+    for rep in range(3):
+        psis = [to_device(wl.psi0, "c64") for wl in wls]
+        b.propagate(psis, 0, 20)
+        grids[3].propagate(other, 0, 7)  # eager work between replays
+        b.check()
+        torch.cuda.synchronize()
+        for i, (p, d) in enumerate(zip(psis, direct)):
+            assert np.array_equal(p.cpu().numpy().astype(np.complex128), d), (rep, i)
+    b.close()
+    for g in grids:
+        g.close()
+
+
+def adjoint_problems():
+    wls = mixed_problems(seed=12, nsteps=24)
+    targets = []
+    for wl in wls:
+        nd = wl.ndim
+        targets.append(W.gaussian(wl.n, wl.xmin, wl.xmax, (0.7,) + (0.0,) * (nd - 1), 1.0, (0.0,) * nd))
+    return wls, targets
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_adjoint_matches_oracle(orc, dtype):
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls, targets = adjoint_problems()
+    ns = 24
+    refs, psiTs, gTs = [], [], []
+    for wl, tg in zip(wls, targets):
+        psiT = orc.schrodinger(wl.psi0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, wl.ebar, nsteps=ns)
+        ov = wl.dv * np.vdot(tg, psiT)
+        gT = 2 * ov * tg * wl.dv
+        refs.append(orc.schrodinger_adjoint(wl.psi0, gT, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, wl.ebar,
+                                            nsteps=ns))
+        if dtype == "c64":
+            psiT = psiT.astype(np.complex64).astype(np.complex128)
+        psiTs.append(psiT)
+        gTs.append(gT)
+    grids = [make_grid(wl, dtype) for wl in wls]
+    psis = [to_device(p, dtype) for p in psiTs]
+    gs = [to_device(g, dtype) for g in gTs]
+    b = sfo.Batch(grids)
+    dEs, dVs = b.adjoint(psis, gs, 0, ns)
+    b.check()
+    torch.cuda.synchronize()
+    tol = GRAD_TOL[dtype]
+    for i, (wl, (g0, dE, dV)) in enumerate(zip(wls, refs)):
+        p0 = psis[i].cpu().numpy().astype(np.complex128)
+        gg = gs[i].cpu().numpy().astype(np.complex128)
+        gdE, gdV = dEs[i].cpu().numpy(), dVs[i].cpu().numpy()
+        errs = (rel_l2(p0, wl.psi0), rel_l2(gg, g0), np.linalg.norm(gdE - dE) / np.linalg.norm(dE),
+                np.linalg.norm((gdV - dV).ravel()) / np.linalg.norm(dV.ravel()))
+        print("%-6s %-12s psi0 %.1e g0 %.1e dE %.1e dV %.1e" % ((dtype, wl.n) + errs), flush=True)
+        assert errs[0] < FWD_TOL[dtype], (wl.n, errs)
+        assert max(errs[1:]) < tol, (wl.n, errs)
+    b.close()
+    for g in grids:
+        g.close()
+
+
+def test_batch_adjoint_equals_single_grid_adjoint():
+    """The batched reverse sweep and the single-grid one agree (c128)."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls, targets = adjoint_problems()
+    wls, targets = wls[:1] + wls[4:6], targets[:1] + targets[4:6]
+    grids = [make_grid(wl, "c128") for wl in wls]
+    rng = np.random.default_rng(3)
+    states = [(rng.standard_normal(wl.psi0.shape) + 1j * rng.standard_normal(wl.psi0.shape)) * 1e-2 + wl.psi0
+              for wl in wls]
+    adjs = [t * 0.5 for t in targets]
+    ps = [to_device(s, "c128") for s in states]
+    gs = [to_device(a, "c128") for a in adjs]
+    b = sfo.Batch(grids)
+    dEs, dVs = b.adjoint(ps, gs, 2, 20)
+    b.check()
+    for i, g in enumerate(grids):
+        p1, g1 = to_device(states[i], "c128"), to_device(adjs[i], "c128")
+        dE1, dV1 = g.adjoint(p1, g1, 2, 20)
+        torch.cuda.synchronize()
+        assert rel_l2(ps[i].cpu().numpy(), p1.cpu().numpy()) < 1e-13
+        assert rel_l2(gs[i].cpu().numpy(), g1.cpu().numpy()) < 1e-13
+        assert np.linalg.norm((dEs[i] - dE1).cpu().numpy()) <= 1e-12 * np.linalg.norm(dE1.cpu().numpy())
+        assert np.linalg.norm((dVs[i] - dV1).cpu().numpy()) <= 1e-12 * np.linalg.norm(dV1.cpu().numpy())
+    b.close()
+    for g in grids:
+        g.close()
+
+
+def test_batch_rejects_unsupported():
+    from paper_1012_3911_amd import sfo
+
+    ok = make_grid(mixed_problems()[3], "c64")
+    cube = W.Workload("c", "schrodinger", (64, 64, 64), (-5.0,) * 3, (5.0,) * 3, 0.01, 1,
+                      np.zeros((64, 64, 64)), np.ones((64, 64, 64), complex))
+    dirac = W.Workload("d", "dirac", (64, 64), (-1.0, -1.0), (1.0, 1.0), 1e-5, 1,
+                       np.zeros((64, 64)), np.ones((4, 64, 64), complex), abar_y=np.zeros((1, 64)))
+    for wl, dtype, status in ((cube, "c64", sfo.SFO_E_UNSUPPORTED), (dirac, "c64", sfo.SFO_E_UNSUPPORTED),
+                              (mixed_problems()[0], "c128", sfo.SFO_E_INVALID)):
+        g = make_grid(wl, dtype)
+        with pytest.raises(sfo.SfoError) as ei:
+            sfo.Batch([ok, g])
+        assert ei.value.status == status
+        g.close()
+    ok.close()
+
+
+def test_batch_small_grids_and_repeated_shapes(orc):
+    """Grids below the usual tile sizes (64-point lines, 64 x 64) and several
+    problems of one shape in one group, against the oracle."""
+    wls = []
+    rng = np.random.default_rng(21)
+    for n in ((64,), (64, 64), (64, 64), (128, 64), (64,)):
+        nd = len(n)
+        lo, hi = (-8.0,) * nd, (8.0,) * nd
+        X = W.mesh(n, lo, hi) if nd > 1 else W.axes(n, lo, hi)
+        V0 = -1.0 / np.sqrt(sum(x**2 for x in X) + rng.uniform(0.5, 2.0))
+        psi0 = W.gaussian(n, lo, hi, (0.0,) * nd, 1.0, tuple(rng.uniform(-1, 1, size=nd)))
+        ebar = 0.02 * rng.uniform(-0.2, 0.2, size=(12, nd))
+        wls.append(W.Workload("s", "schrodinger", n, lo, hi, 0.02, 12, V0, psi0, ebar=ebar))
+    got = run_batch(wls, "c128", 0, 12)
+    for wl, g in zip(wls, got):
+        assert rel_l2(g, oracle_run(orc, wl, nsteps=12)) < 1e-12
+
+
+def test_control_batch_full_size(orc):
+    """The 64-problem control batch (1-D 512..8192, 2-D 256^2..1024^2,
+    complex64, 400 steps) in one batched call: norm conservation for every
+    problem and oracle parity for the smallest and largest of each kind."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls, targets, ctl = W.control_batch()
+    grids = [make_grid(wl, "c64") for wl in wls]
+    psis = [to_device(wl.psi0, "c64") for wl in wls]
+    n0 = [g.norm(p) for g, p in zip(grids, psis)]
+    b = sfo.Batch(grids)
+    b.propagate(psis, 0, wls[0].nsteps)
+    b.check()
+    torch.cuda.synchronize()
+    for g, p, a in zip(grids, psis, n0):
+        assert abs(g.norm(p) / a - 1) < 1e-5
+    pick = set()
+    for nd in (1, 2):
+        idx = [i for i, wl in enumerate(wls) if wl.ndim == nd]
+        pick.add(min(idx, key=lambda i: wls[i].npoints))
+        pick.add(max(idx, key=lambda i: wls[i].npoints))
+    for i in sorted(pick):
+        ref = oracle_run(orc, wls[i])
+        err = rel_l2(psis[i].cpu().numpy(), ref)
+        print("control batch problem %d %s rel L2 %.2e" % (i, wls[i].n, err), flush=True)
+        assert err < 1e-5
+    b.close()
+    for g in grids:
+        g.close()
