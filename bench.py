@@ -12,7 +12,14 @@ x-transform, merged potential factor, forward x-transform) and the column
 pass (forward y-transform, kinetic factor, inverse y-transform).  `value` is
 the complex64 path (FP32 storage and butterflies, FP64 phases and
 reductions); the complex128 path, fused and in the paper's unfused
-five-launch form, is reported beside it.
+five-launch form, is reported beside it, and so are the forward run plus
+reverse sweep (adjoint) of the same workload and the 64-problem batched
+control workload (forward, and forward + reverse sweep).
+
+Roofline: the dominant pass's algorithmic bytes per launch divided by its
+average launch duration, timed with HIP events around back-to-back launches
+on the grid's stream; `traffic` is the HBM bytes per launch measured with
+rocprofv3 counters for the same kernel sources (null otherwise).
 
 Prints ONE JSON line.  --gpus N with N > 1 is refused: the library runs on
 one GPU.
@@ -31,6 +38,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+# HBM bytes per launch of the 2048 x 2048 complex64 passes, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
+# counters read for a plain 512 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE
+# x 1); keyed by pass and tile-shape number.  Valid only for the kernel
+# sources they were taken on: a different fingerprint reports null.
+TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
+_KIB = 1024
+MEASURED_TRAFFIC = {
+    "sources_sha256": "454ed965d3b84fc61bec572a6e75fb4f7ef46ec089b679420d26c9e51393fd72",
+    # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
+    "row/0": (24856, 32768), "row/1": (24846, 32768), "row/2": (24971, 32768), "row/3": (24858, 32768),
+    "row/4": (38440, 65911), "row/5": (24800, 32768), "row/6": (24805, 32768), "row/7": (24801, 32768),
+    "row/8": (24858, 32768), "row/9": (24862, 32768), "row/10": (24992, 32768), "row/11": (24864, 32768),
+    "column/0": (16797, 33003), "column/1": (16790, 32777), "column/2": (16790, 35454),
+    "column/4": (16790, 32833), "column/5": (16788, 33046), "column/7": (16968, 33747),
+    "column/8": (16786, 34473),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
+
+
+def measured_traffic(kind, variant):
+    v = MEASURED_TRAFFIC.get("%s/%d" % (kind, variant))
+    if v is None:
+        return None
+    return (FETCH_SCALE * v[0] + WRITE_SCALE * v[1]) * _KIB
+
+
+def sources_fingerprint():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1012_3911_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -78,11 +121,15 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g.propagate(psi, 0, wl.nsteps)
     drift = g.norm(psi) / n0 - 1
     final = psi.cpu().numpy()
-    # per-kernel durations: the same launches again with HIP events around each pass
+    # per-kernel durations: back-to-back launches of each pass between two HIP
+    # events on the grid's stream, and the timed sequence again with an event
+    # pair around every launch (which adds the dispatch gap to each)
+    kern = {name: g.time_pass(kind, 200) for name, kind in
+            (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
     g.profile(True)
     run_steps(g, psi, min(steps, 2 * wl.nsteps), wl.nsteps)
-    kern = {name: g.profile_read(kind) for name, kind in
-            (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
+    kern_ev = {name: g.profile_read(kind) for name, kind in
+               (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
     g.profile(False)
     fa = None
     if dtype == "c64" and not flags:
@@ -101,7 +148,8 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g.close()
     del psi
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, plan=plan, fwd_adj_seconds=fa)
+    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, kernels_ev=kern_ev, plan=plan,
+                fwd_adj_seconds=fa)
 
 
 def bench_batch(reps=3):
@@ -220,12 +268,17 @@ def main():
     # row pass additionally reads V0
     alg = {"column": 2 * bytes_state, "row": 2 * bytes_state + bytes_v0}
     kstats = {}
-    for k, (cnt, tot) in r["kernels"].items():
-        if cnt:
-            avg = tot / cnt
-            kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches=cnt)
-    dom = max(kstats, key=lambda k: kstats[k]["avg_us"] * kstats[k]["launches"])
+    for k, avg in r["kernels"].items():
+        cnt, tot = r["kernels_ev"][k]
+        kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches_per_step=1,
+                         avg_us_event_per_launch=1e3 * tot / cnt if cnt else None)
+    dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
     achieved = kstats[dom]["gbs"]
+    plan = list(r["plan"])
+    variant = {"row": plan[0], "column": plan[1]}[dom]
+    traffic = None
+    if head == "c64" and wl.n == (2048, 2048) and sources_fingerprint() == MEASURED_TRAFFIC["sources_sha256"]:
+        traffic = measured_traffic(dom, variant)
     err_vs_c128 = None
     if "c64" in res and "c128" in res:
         a, b = res["c64"]["final"].astype(np.complex128), res["c128"]["final"]
@@ -251,12 +304,13 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_colpass" if dom == "column" else "k_xpass",
+            "kernel": ("k_colpass" if dom == "column" else "k_xpass") + " (tile shape %d)" % variant,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "algorithmic_bytes": alg[dom],
         },
         "step_model_gbs": step_bytes / (ms * 1e-3) / 1e9,
         "step_model_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,

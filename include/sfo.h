@@ -210,6 +210,15 @@ enum {
 sfo_status sfo_profile_enable(sfo_grid g, int32_t on);
 sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *total_ms);
 
+/* Average duration in milliseconds of one launch of the grid's current
+ * shape of a pass (SFO_KERNEL_ROW: inverse x-transform, potential factor,
+ * forward x-transform; SFO_KERNEL_COLUMN / ZCOLUMN: transform, kinetic
+ * factor, inverse transform), from `reps` back-to-back launches on a scratch
+ * state (allocated and freed by the call) between two HIP events on the
+ * grid's stream.  Unlike sfo_profile_read, no event sits between launches.
+ * 2-D and 3-D Schroedinger grids; synchronises the stream. */
+sfo_status sfo_time_pass(sfo_grid g, int32_t kind, int32_t reps, double *avg_ms);
+
 /* Description of the last failure on the calling thread ("" if none). */
 const char *sfo_last_error(void);
 

@@ -455,53 +455,102 @@ template <typename F> double time_launches(sfo_grid g, hipEvent_t a, hipEvent_t 
     return ms;
 }
 
-template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
+// Back-to-back launches of one pass shape on a scratch state (row pass:
+// inverse transform, potential factor, forward transform; axis-ax pass:
+// transform, kinetic factor on the last axis, inverse transform).
+template <typename R> double time_row(sfo_grid g, int v, cx<R> *psi, hipEvent_t ea, hipEvent_t eb, int reps)
+{
+    const PhaseArgs ph = phase_args(g, -1, 0, +1);
+    return time_launches(g, ea, eb, reps, [&] {
+        return launch_xpass<R>(v, (int)g->n[0], 1, StatePtrs<R>{{psi, nullptr}}, g->n[1] * g->n[2], (int)g->n[1],
+                               g->V0, (const void *const *)g->tw[0], ph, GradArgs{}, M_INV | M_PHASE | M_FWD, g->st);
+    });
+}
+
+template <typename R>
+double time_col(sfo_grid g, int ax, int v, cx<R> *psi, hipEvent_t ea, hipEvent_t eb, int reps)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncols = ax == 1 ? nx : nx * ny;
+    const int nslab = (ax == 1 && g->ndim == 3) ? (int)nz : 1;
+    const bool kinetic = ax == g->ndim - 1;
+    const KinArgs k{g->kin[0], ax == 2 ? g->kin[1] : g->one, g->kin[ax], (int)nx, 1};
+    const KinArgs none{g->one, g->one, g->one, 1, 1};
+    return time_launches(g, ea, eb, reps, [&] {
+        return launch_colpass<R>(v, (int)g->n[ax], 1, StatePtrs<R>{{psi, nullptr}}, ncols, ncols, nslab, nx * ny,
+                                 (const void *const *)g->tw[ax], kinetic ? k : none,
+                                 kinetic ? (M_FWD | M_KIN | M_INV) : M_FWD, g->st);
+    });
+}
+
+// Scratch state and an event pair for the timing helpers.
+struct TimingScratch {
+    void *mem = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    ~TimingScratch()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        (void)hipFree(mem);
+    }
+};
+
+template <typename R> sfo_status timing_setup(sfo_grid g, TimingScratch &ts)
 {
     const size_t bytes = sizeof(cx<R>) * (size_t)g->ntot * g->ncomp;
-    void *scratch = nullptr;
-    HIP_TRY(hipMalloc(&scratch, bytes));
-    hipEvent_t ea = nullptr, eb = nullptr;
-    hipError_t he = hipMemsetAsync(scratch, 0, bytes, g->st);
-    if (he == hipSuccess) he = hipEventCreate(&ea);
-    if (he == hipSuccess) he = hipEventCreate(&eb);
-    if (he != hipSuccess) {
-        (void)hipFree(scratch);
-        if (ea) (void)hipEventDestroy(ea);
-        return fail(SFO_E_HIP, "autotune setup: %s", hipGetErrorString(he));
-    }
-    cx<R> *psi = (cx<R> *)scratch;
-    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
-    const PhaseArgs ph = phase_args(g, -1, 0, +1);
+    HIP_TRY(hipMalloc(&ts.mem, bytes));
+    HIP_TRY(hipMemsetAsync(ts.mem, 0, bytes, g->st));
+    HIP_TRY(hipEventCreate(&ts.a));
+    HIP_TRY(hipEventCreate(&ts.b));
+    return SFO_OK;
+}
+
+template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
+{
+    TimingScratch ts;
+    sfo_status s = timing_setup<R>(g, ts);
+    if (s) return s;
+    cx<R> *psi = (cx<R> *)ts.mem;
+    // best of three trials per shape: one trial is easily disturbed
+    auto best_of = [&](auto &&timer) {
+        double m = 1e30;
+        for (int trial = 0; trial < 3; ++trial) {
+            const double t = timer();
+            if (t < 0) return -1.0;
+            m = std::min(m, t);
+        }
+        return m;
+    };
     double best = 1e30;
     for (int v = 0; v < kNumRowVariants; ++v) {
-        if (!xpass_variant_ok<R>(v, (int)nx)) continue;
-        const double ms = time_launches(g, ea, eb, reps, [&] {
-            return launch_xpass<R>(v, (int)nx, 1, StatePtrs<R>{{psi, nullptr}}, ny * nz, (int)ny, g->V0,
-                                   (const void *const *)g->tw[0], ph, GradArgs{}, M_INV | M_PHASE | M_FWD, g->st);
-        });
+        if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
+        const double ms = best_of([&] { return time_row<R>(g, v, psi, ts.a, ts.b, reps); });
         if (ms >= 0 && ms < best) { best = ms; g->row_var = v; }
     }
     for (int ax = 1; ax < g->ndim; ++ax) {
-        const int64_t n = g->n[ax];
-        const int64_t ncols = ax == 1 ? nx : nx * ny;
-        const int nslab = (ax == 1 && g->ndim == 3) ? (int)nz : 1;
-        const bool kinetic = ax == g->ndim - 1;
-        KinArgs k{g->kin[0], ax == 2 ? g->kin[1] : g->one, g->kin[ax], (int)nx, 1};
-        KinArgs none{g->one, g->one, g->one, 1, 1};
+        const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
         best = 1e30;
         for (int v = 0; v < kNumColVariants; ++v) {
-            if (!colpass_variant_ok<R>(v, (int)n, ncols)) continue;
-            const double ms = time_launches(g, ea, eb, reps, [&] {
-                return launch_colpass<R>(v, (int)n, 1, StatePtrs<R>{{psi, nullptr}}, ncols, ncols, nslab, nx * ny,
-                                         (const void *const *)g->tw[ax], kinetic ? k : none,
-                                         kinetic ? (M_FWD | M_KIN | M_INV) : M_FWD, g->st);
-            });
+            if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+            const double ms = best_of([&] { return time_col<R>(g, ax, v, psi, ts.a, ts.b, reps); });
             if (ms >= 0 && ms < best) { best = ms; g->col_var[ax] = v; }
         }
     }
-    (void)hipEventDestroy(ea);
-    (void)hipEventDestroy(eb);
-    (void)hipFree(scratch);
+    return SFO_OK;
+}
+
+template <typename R> sfo_status time_pass_impl(sfo_grid g, int kind, int reps, double *avg_ms)
+{
+    TimingScratch ts;
+    sfo_status s = timing_setup<R>(g, ts);
+    if (s) return s;
+    cx<R> *psi = (cx<R> *)ts.mem;
+    double ms = -1.0;
+    if (kind == SFO_KERNEL_ROW) ms = time_row<R>(g, g->row_var, psi, ts.a, ts.b, reps);
+    else if (kind == SFO_KERNEL_COLUMN) ms = time_col<R>(g, 1, g->col_var[1], psi, ts.a, ts.b, reps);
+    else ms = time_col<R>(g, 2, g->col_var[2], psi, ts.a, ts.b, reps);
+    if (ms < 0) return fail(SFO_E_HIP, "timing launches failed: %s", hipGetErrorString(hipGetLastError()));
+    *avg_ms = ms / reps;
     return SFO_OK;
 }
 
@@ -1141,6 +1190,17 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps)
     std::lock_guard<std::mutex> lk(g_plan_mu);
     store_plan(key, {g->row_var, g->col_var[1], g->col_var[2]});
     return SFO_OK;
+}
+
+sfo_status sfo_time_pass(sfo_grid g, int32_t kind, int32_t reps, double *avg_ms)
+{
+    if (!g || !avg_ms) return fail(SFO_E_INVALID, "null grid or output");
+    if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
+        return fail(SFO_E_UNSUPPORTED, "pass timing is for 2-D and 3-D Schroedinger grids");
+    if (reps < 1) return fail(SFO_E_INVALID, "reps must be positive");
+    if (kind != SFO_KERNEL_ROW && kind != SFO_KERNEL_COLUMN && !(kind == SFO_KERNEL_ZCOLUMN && g->ndim == 3))
+        return fail(SFO_E_INVALID, "no pass of kind %d on this grid", kind);
+    return g->c128 ? time_pass_impl<double>(g, kind, reps, avg_ms) : time_pass_impl<float>(g, kind, reps, avg_ms);
 }
 
 sfo_status sfo_get_plan(sfo_grid g, int32_t *plan)

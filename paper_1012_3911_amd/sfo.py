@@ -54,7 +54,8 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_set_vector_potential", "sfo_step", "sfo_propagate", "sfo_adjoint", "sfo_norm",
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
-           "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_last_error", "sfo_version"]
+           "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_last_error",
+           "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "sfo_set_plan": [P, P],
         "sfo_profile_enable": [P, I32],
         "sfo_profile_read": [P, I32, P, P],
+        "sfo_time_pass": [P, I32, I32, P],
         "sfo_create_batch": [P, I32, P, ctypes.POINTER(P)],
         "sfo_destroy_batch": [P],
         "sfo_propagate_batch": [P, P, I64, I64],
@@ -249,6 +251,12 @@ class Grid:
         _check(_lib.sfo_profile_read(self._h, int(kind), ctypes.byref(cnt), ctypes.byref(ms)),
                "sfo_profile_read")
         return cnt.value, ms.value
+
+    def time_pass(self, kind: int, reps: int = 100) -> float:
+        """Average milliseconds per launch of one pass shape, from back-to-back launches."""
+        ms = ctypes.c_double()
+        _check(_lib.sfo_time_pass(self._h, int(kind), int(reps), ctypes.byref(ms)), "sfo_time_pass")
+        return ms.value
 
     def fft(self, psi, sign: int = -1):
         _check(_lib.sfo_fft(self._h, self._state(psi), int(sign)), "sfo_fft")

@@ -84,4 +84,5 @@ def test_null_arguments(lib):
     assert lib.sfo_adjoint_batch(None, None, None, 0, 1, None, None) == -1
     assert lib.sfo_batch_set_graph(None, 1) == -1
     assert lib.sfo_batch_check(None) == -1
+    assert lib.sfo_time_pass(None, 0, 10, None) == -1
     assert lib.sfo_version().decode().startswith("sfo")

@@ -241,3 +241,24 @@ def test_2d_full_size_full_run_properties():
     assert abs(out["c128"][1]) < 1e-12
     assert abs(out["c64"][1]) < C64_DRIFT
     assert rel_l2(out["c64"][0], out["c128"][0]) < C64_TOL
+
+
+def test_time_pass_reports_the_current_shapes():
+    """sfo_time_pass: positive durations for the row and column passes of a
+    2-D grid, refused for a 1-D grid (which has no separate passes)."""
+    from paper_1012_3911_amd import sfo
+
+    n, lo, hi = (256, 128), (-10.0, -10.0), (10.0, 10.0)
+    wl = W.Workload("t", "schrodinger", n, lo, hi, 0.02, 1, np.zeros(n[::-1]), np.ones(n[::-1], complex))
+    g = make_grid(wl, "c64")
+    for kind in (sfo.KERNEL_ROW, sfo.KERNEL_COLUMN):
+        ms = g.time_pass(kind, 5)
+        assert 0.0 < ms < 100.0
+    with pytest.raises(sfo.SfoError):
+        g.time_pass(sfo.KERNEL_ZCOLUMN, 5)
+    g.close()
+    w1 = W.Workload("l", "schrodinger", (256,), (-5.0,), (5.0,), 0.01, 1, np.zeros(256), np.ones(256, complex))
+    g1 = make_grid(w1, "c64")
+    with pytest.raises(sfo.SfoError):
+        g1.time_pass(sfo.KERNEL_ROW, 5)
+    g1.close()
