@@ -80,11 +80,7 @@ __device__ __forceinline__ void group_row_args(const GroupArgs<R> &grp, StatePtr
         ga.acc = P.dV;
         ga.wacc = grp.wmul * P.aV_half;
         ga.acc_init = grp.acc_init;
-        ga.part = P.part;
-        ga.count = P.count;
-        ga.mom = P.mom + 3 * grp.jmom;
-        ga.slot = (int)blockIdx.x;
-        ga.nslots = (int)gridDim.x;
+        ga.part = P.part + 3 * (int64_t)gridDim.x * grp.jmom;
     }
 }
 
@@ -108,32 +104,13 @@ __device__ __forceinline__ void block_sum3(double (&v)[3], double (*red)[3])
     __syncthreads();
 }
 
-// Work-group partial moments -> part[slot]; the last of the nslots groups to
-// finish sums all partials in a fixed order into out[0..2] and re-arms the
-// counter.
-__device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], double *part, unsigned *count,
-                                          double *out, unsigned slot, unsigned nslots)
+// Work-group moment partials -> part[3 blockIdx.x + a]; the slots are summed
+// by a later kernel, so no fence or counter is needed here.
+__device__ __forceinline__ void block_part3(double (&v)[3], double (*red)[3], double *part)
 {
     block_sum3(v, red);
-    __shared__ unsigned last;
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) part[3 * slot + a] = v[a];
-        __threadfence();
-        last = atomicAdd(count, 1u) == nslots - 1 ? 1u : 0u;
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        double s[3] = {0.0, 0.0, 0.0};
-        for (unsigned i = threadIdx.x; i < nslots; i += blockDim.x)
-            for (int a = 0; a < 3; ++a) s[a] += __builtin_nontemporal_load(part + 3 * i + a);
-        block_sum3(s, red);
-        if (threadIdx.x == 0) {
-            for (int a = 0; a < 3; ++a) out[a] = s[a];
-            *count = 0u;
-        }
-    }
-    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) part[3 * blockIdx.x + a] = v[a];
 }
 
 // --------------------------------------------------------------- row pass --
@@ -147,7 +124,7 @@ __device__ __forceinline__ void grid_sum3(double (&v)[3], double (*red)[3], doub
 // exp(-i sgn e_x T dx)) advanced by FP64 complex multiplication.
 // M_GRAD (NS = 2) additionally forms b = Im(conj(g) psi) at this step
 // boundary in real space: acc += w b (the dL/dV0 accumulator) and the
-// moments sum_x (x b, y b, z b) reduced over the grid into ga.mom.
+// moments sum_x (x b, y b, z b), summed over the work-group into ga.part.
 template <typename R, int N, int RAD, int NS, int NV>
 __device__ __forceinline__ void row_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t row,
                                          int t)
@@ -183,14 +160,24 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
     for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
 }
 
+// This row's dL/dV0 accumulator values (zero when the boundary starts the sum).
+template <typename R, int N, int RAD, int NV>
+__device__ __forceinline__ void row_load_acc(double (&accv)[NV], const GradArgs &ga, int64_t row, int t)
+{
+    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
+    constexpr int T = LineShape<N, RAD>::T;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) accv[m] = (ga.acc && !ga.acc_init) ? ga.acc[row * N + t + m * T] : 0.0;
+}
+
 // The register part of a row tile: inverse x-transform, potential factor,
 // gradient partials (mom accumulates this row's moments), forward
 // x-transform.  sh: this row's LDS exchange region; tw: twiddle table
 // (global or an LDS copy).
 template <typename R, int N, int RAD, int NS, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
-                                         const VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh,
-                                         int t, const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph,
+                                         const VStore<R> (&vv)[NV], const double (&accv)[NV], int64_t row, int ny,
+                                         cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph,
                                          const GradArgs &ga, int mode, double (&mom)[3])
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
@@ -283,10 +270,7 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
             const int x = t + m * T;
             const cx<R> ps = v[0][m], gq = v[NS - 1][m];
             const double b = (double)gq.re * (double)ps.im - (double)gq.im * (double)ps.re;
-            if (ga.acc) {
-                double *ap = ga.acc + row * N + x;
-                *ap = (ga.acc_init ? 0.0 : *ap) + ga.wacc * b;
-            }
+            if (ga.acc) ga.acc[row * N + x] = accv[m] + ga.wacc * b;
             sb += b;
             mom[0] += (ph.xmin[0] + (double)x * ph.dx[0]) * b;
         }
@@ -310,17 +294,15 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     cx<R> *sh = lds + line * RowMap<R, RAD>::slots(N);
     cx<R> v[NS][RV];
     VStore<R> vv[RV];
+    double accv[RV];
     row_load<R, N, RAD, NS>(v, S, row, t);
-    // the potential loads complete under the inverse transform
+    // the potential (and accumulator) loads complete under the inverse transform
     if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
+    if (NS == 2 && (mode & M_GRAD)) row_load_acc<R, N, RAD>(accv, ga, row, t);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom);
+    row_body<R, N, RAD, NS>(v, vv, accv, row, ny, sh, t, tw, ph, ga, mode, mom);
     row_store<R, N, RAD, NS>(v, S, row, t);
-    if (NS == 2 && (mode & M_GRAD)) {
-        const unsigned slot = ga.nslots ? (unsigned)ga.slot : blockIdx.x;
-        const unsigned nslots = ga.nslots ? (unsigned)ga.nslots : gridDim.x * gridDim.y;
-        grid_sum3(mom, red, ga.part, ga.count, ga.mom, slot, nslots);
-    }
+    if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
 template <typename R, int N, int RAD, int THREADS, int WPE, int NS>
@@ -367,11 +349,13 @@ k_xpass_pipe(StatePtrs<R> S, int ny, int64_t ntiles, const VStore<R> *__restrict
     for (int i = 0; i < PIPE && tile < ntiles; ++i, tile += G) {
         const int64_t row = tile * ROWS + line;
         VStore<R> vv[RV];
+        double accv[RV];
         if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
+        if (NS == 2 && (mode & M_GRAD)) row_load_acc<R, N, RAD>(accv, ga, row, t);
         const bool more = i + 1 < PIPE && tile + G < ntiles;
         cx<R> vn[NS][RV];
         if (more) row_load<R, N, RAD, NS>(vn, S, (tile + G) * ROWS + line, t);
-        row_body<R, N, RAD, NS>(v, vv, row, ny, sh, t, twl, ph, ga, mode, mom);
+        row_body<R, N, RAD, NS>(v, vv, accv, row, ny, sh, t, twl, ph, ga, mode, mom);
         row_store<R, N, RAD, NS>(v, S, row, t);
         if (more)
 #pragma unroll
@@ -379,7 +363,7 @@ k_xpass_pipe(StatePtrs<R> S, int ny, int64_t ntiles, const VStore<R> *__restrict
 #pragma unroll
                 for (int m = 0; m < RV; ++m) v[q][m] = vn[q][m];
     }
-    if (NS == 2 && (mode & M_GRAD)) grid_sum3(mom, red, ga.part, ga.count, ga.mom, blockIdx.x, gridDim.x);
+    if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
 // ------------------------------------------------------------ column pass --

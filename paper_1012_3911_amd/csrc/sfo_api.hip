@@ -72,12 +72,9 @@ struct sfo_grid_s {
     double *kvec[3] = {nullptr, nullptr, nullptr}; // per-axis wave numbers (Dirac)
     double2 *one = nullptr;                        // {1, 0}
     double *red = nullptr;                         // reduction partials + result
-    // adjoint scratch: per-boundary moments, per-work-group partials, a group counter
-    double *mom = nullptr;
-    int64_t mom_cap = 0;
+    // adjoint scratch: moment partials per step boundary and row work-group
     double *part = nullptr;
     int64_t part_cap = 0;
-    unsigned *count = nullptr;
     // kernel timing: event pairs per kernel kind while profiling is on
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
@@ -113,9 +110,7 @@ void free_grid(sfo_grid g)
     }
     (void)hipFree(g->one);
     (void)hipFree(g->red);
-    (void)hipFree(g->mom);
     (void)hipFree(g->part);
-    (void)hipFree(g->count);
     delete g;
 }
 
@@ -574,25 +569,18 @@ template <typename R> void default_plan(sfo_grid g)
 template <typename R>
 sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV)
 {
-    const int64_t need_mom = 3 * (nsteps + 1);
-    if (g->mom_cap < need_mom) {
-        HIP_TRY(hipStreamSynchronize(g->st));
-        (void)hipFree(g->mom);
-        g->mom = nullptr;
-        HIP_TRY(hipMalloc(&g->mom, sizeof(double) * need_mom));
-        g->mom_cap = need_mom;
-    }
+    // moment partials: boundary n (0..nsteps) x slot x 3; the 1-D kernel writes one slot per boundary
     const int64_t nrows = g->n[1] * g->n[2];
-    if (g->ndim >= 2 && g->part_cap < 3 * nrows) {
+    const int nslots = g->ndim == 1 ? 1 : xpass_groups<R>(g->row_var, (int)g->n[0], nrows);
+    if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
+    const int64_t need = 3 * (int64_t)nslots * (nsteps + 1);
+    if (g->part_cap < need) {
         HIP_TRY(hipStreamSynchronize(g->st));
         (void)hipFree(g->part);
         g->part = nullptr;
-        HIP_TRY(hipMalloc(&g->part, sizeof(double) * 3 * nrows));
-        g->part_cap = 3 * nrows;
-    }
-    if (!g->count) {
-        HIP_TRY(hipMalloc(&g->count, sizeof(unsigned)));
-        HIP_TRY(hipMemset(g->count, 0, sizeof(unsigned)));
+        g->part_cap = 0;
+        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
+        g->part_cap = need;
     }
     const double wbase = g->d.dt / (2.0 * g->d.hbar);
     if (g->ndim == 1) {
@@ -608,31 +596,29 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
         a.dir = -1;
         HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
             return launch_1d_adjoint<R>((int)g->n[0], (cx<R> *)psi, (cx<R> *)gv, g->V0, g->tw[0][1], a, wbase, dV,
-                                        g->mom, g->st);
+                                        g->part, g->st);
         }));
     } else {
         GradArgs ga{};
         ga.acc = dV;
-        ga.part = g->part;
-        ga.count = g->count;
         sfo_status s;
         auto st_of = [&](int64_t j) { return step0 + j; };
         ga.wacc = wbase;
         ga.acc_init = 1;
-        ga.mom = g->mom + 3 * nsteps;
+        ga.part = g->part + 3 * (int64_t)nslots * nsteps;
         const int first = nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD;
         if ((s = schro_xpass<R>(g, psi, gv, -1, nsteps > 0 ? st_of(nsteps - 1) : -1, -1, first, ga))) return s;
         for (int64_t j = nsteps - 1; j >= 0; --j) {
             if ((s = schro_colpasses<R>(g, psi, gv, M_FWD | M_KIN | M_INV, -1))) return s;
             ga.acc_init = 0;
             ga.wacc = (j > 0 ? 2.0 : 1.0) * wbase;
-            ga.mom = g->mom + 3 * j;
+            ga.part = g->part + 3 * (int64_t)nslots * j;
             if ((s = schro_xpass<R>(g, psi, gv, st_of(j), j > 0 ? st_of(j - 1) : -1, -1,
                                     M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), ga)))
                 return s;
         }
     }
-    if (dE) HIP_TRY(launch_ebar_grad(g->mom, nsteps, g->ndim, 1.0 / (2.0 * g->d.hbar), dE, g->st));
+    if (dE) HIP_TRY(launch_ebar_grad(g->part, nslots, nsteps, g->ndim, 1.0 / (2.0 * g->d.hbar), dE, g->st));
     return SFO_OK;
 }
 
@@ -757,7 +743,6 @@ struct sfo_batch_s {
     int *ids_d = nullptr;
     void *probs_d = nullptr;      // BatchProb<R>[count]
     std::vector<char> probs_h;    // what probs_d holds
-    unsigned *counts = nullptr;   // per problem: reduction counter of the reverse sweep
     double *work = nullptr;       // reverse sweep: moments and partials
     int64_t work_cap = 0;
     bool use_graph = true;
@@ -781,7 +766,6 @@ void free_batch(sfo_batch b)
     if (b->side) (void)hipStreamDestroy(b->side);
     (void)hipFree(b->ids_d);
     (void)hipFree(b->probs_d);
-    (void)hipFree(b->counts);
     (void)hipFree(b->work);
     delete b;
 }
@@ -816,15 +800,18 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
         q.inv_2hbar = 1.0 / (2.0 * g->d.hbar);
         q.v0max = g->v0max;
         q.V0 = (decltype(q.V0))g->V0;
-        q.count = b->counts + i;
+        q.gslots = 1;
+        if (g->ndim == 2) {
+            for (const auto &G : b->groups)
+                if (G.ndim == 2 && G.nx == q.nx && G.ny == q.ny)
+                    q.gslots = std::max(1, xpass_groups<R>(G.rep->row_var, q.nx, q.ny));
+        }
         if (gadj) {
             q.gadj = (cx<R> *)gadj[i];
             q.dE = dE ? dE[i] : nullptr;
             q.dV = dV ? dV[i] : nullptr;
-            q.mom = b->work ? b->work + off : nullptr;
-            off += 3 * (nsteps + 1);
             q.part = b->work ? b->work + off : nullptr;
-            off += 3 * g->n[1];  // at least one slot per row work-group
+            off += 3 * (int64_t)q.gslots * (nsteps + 1);
         }
     }
     *work_need = off;
@@ -851,7 +838,6 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
         return a;
     };
     hipError_t e = hipSuccess;
-    if (dir < 0) e = launch_batch_reset(b->counts, (int)b->grids.size(), s);
     // 1-D problems: one whole-run launch per length
     hipStream_t s1 = side ? side : s;
     if (e == hipSuccess && side) {
@@ -1293,8 +1279,6 @@ sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stre
     if (e == hipSuccess) e = hipMemcpy(b->ids_d, b->ids.data(), sizeof(int) * b->ids.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc(&b->probs_d, (c128 ? sizeof(BatchProb<double>) : sizeof(BatchProb<float>)) * count);
-    if (e == hipSuccess) e = hipMalloc(&b->counts, sizeof(unsigned) * count);
-    if (e == hipSuccess) e = hipMemset(b->counts, 0, sizeof(unsigned) * count);
     if (e != hipSuccess) return guard(e);
     *out = b;
     return SFO_OK;

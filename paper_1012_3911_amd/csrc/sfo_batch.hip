@@ -4,39 +4,32 @@
 // problem of a group, the problem index being a grid dimension (see
 // GroupArgs), so that a 400-step run of a batch costs a few launches per step
 // in all, not a few per problem; the whole sequence is captured in a HIP
-// graph by the host (sfo_api.hip).  This file holds the two small kernels
-// that only batches need.
+// graph by the host (sfo_api.hip).  This file holds the small kernel that
+// only batches need.
 #include <algorithm>
 
 #include "sfo_batch.h"
 
 namespace sfo {
 
-__global__ void k_batch_reset(unsigned *count, int n)
-{
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x))
-        count[i] = 0u;
-}
-
-// dL/dEbar[s][a] = (mom[s+1][a] + mom[s][a]) / (2 hbar), one grid row per problem.
+// dL/dEbar[s][a] = (M[s+1][a] + M[s][a]) / (2 hbar), M summed over each
+// problem's partial slots in slot order; one grid row per problem.
 template <typename R> __global__ void k_batch_ebar_grad(const BatchProb<R> *__restrict__ probs, int64_t nsteps)
 {
     const BatchProb<R> &P = probs[blockIdx.y];
     if (!P.dE) return;
-    const int nd = P.ndim;
+    const int nd = P.ndim, ns = P.gslots;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps * nd;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = i / nd;
         const int a = (int)(i % nd);
-        P.dE[i] = (P.mom[3 * (s + 1) + a] + P.mom[3 * s + a]) * P.inv_2hbar;
+        double m1 = 0.0, m0 = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            m1 += P.part[((s + 1) * ns + k) * 3 + a];
+            m0 += P.part[(s * ns + k) * 3 + a];
+        }
+        P.dE[i] = (m1 + m0) * P.inv_2hbar;
     }
-}
-
-hipError_t launch_batch_reset(unsigned *count, int n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)std::min(64, (n + 255) / 256)), dim3(256), 0, st, count, n);
-    return hipGetLastError();
 }
 
 template <typename R>

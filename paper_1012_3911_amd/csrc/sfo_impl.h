@@ -29,11 +29,7 @@ struct GradArgs {
     double *acc;       // dL/dV0 accumulator (FP64, one per point) or null
     double wacc;       // weight of this boundary in acc
     int acc_init;      // 1: overwrite acc instead of adding
-    double *part;      // per-work-group partial moments, 3 per group
-    unsigned *count;   // groups finished (0 on entry; the last group resets it)
-    double *mom;       // out: sum_x (x, y, z) b over the grid
-    int slot, nslots;  // nslots > 0: this group's partial slot and the slot count
-                       // (persistent launches); 0: block index and grid size
+    double *part;      // this boundary's moment partials: 3 per work-group (slot = blockIdx.x)
 };
 
 // Real-space phase of a row pass: theta(x) = aV * V0(x) + e . x, applied as
@@ -106,9 +102,8 @@ template <typename R> struct BatchProb {
     typename std::conditional<sizeof(R) == 4, const float, const double>::type *V0;
     double *dV;                        // dL/dV0 (N points) or null
     double *dE;                        // dL/dEbar (nsteps x ndim) or null
-    double *mom;                       // per boundary: sum_x (x, y, z) b, 3 (nsteps + 1)
-    double *part;                      // per row work-group partial moments
-    unsigned *count;                   // row work-groups finished in the current reduction
+    double *part;                      // moment partials: (nsteps + 1) boundaries x gslots x 3
+    int gslots;                        // partial slots per boundary (row work-groups; 1 for 1-D)
 };
 
 // Per-launch part of a grouped pass (probs == null: an ordinary launch).
@@ -157,9 +152,14 @@ hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const
                              double wbase, double *acc, double *mom, hipStream_t st,
                              const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
 
-// dL/dEbar[s][a] = (mom[s+1][a] + mom[s][a]) * scale for s < nsteps (mom: (nsteps+1) x 3).
-hipError_t launch_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out,
+// dL/dEbar[s][a] = (M[s+1][a] + M[s][a]) * scale for s < nsteps, where
+// M[j][a] = sum over the nslots partials part[(j nslots + i) 3 + a], summed in
+// slot order (deterministic).
+hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int ndim, double scale, double *out,
                             hipStream_t st);
+
+// Number of work-groups (= gradient partial slots) of a row pass launch.
+template <typename R> int xpass_groups(int variant, int N, int64_t nrows);
 
 // Host copy of the stage layout of LineShape<N, RAD>: (radix, span) per stage.
 void line_stages(int N, int RAD, int *radix, int *span, int *nst);

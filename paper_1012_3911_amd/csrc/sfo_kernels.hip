@@ -55,19 +55,24 @@ __global__ void __launch_bounds__((LineShape<N, RAD>::T))
     if (grp.probs) {
         const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.x]];
         group_1d_args(P, a);
-        adj1d_tile<R, VT, N, RAD>(P.psi, P.gadj, (const VT *)P.V0, tw, a, P.aV_half, P.dV, P.mom, sh, red,
+        adj1d_tile<R, VT, N, RAD>(P.psi, P.gadj, (const VT *)P.V0, tw, a, P.aV_half, P.dV, P.part, sh, red,
                                   threadIdx.x);
         return;
     }
     adj1d_tile<R, VT, N, RAD>(psi, gv, V0, tw, a, wbase, acc_out, mom, sh, red, threadIdx.x);
 }
 
-__global__ void k_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out)
+__global__ void k_ebar_grad(const double *part, int nslots, int64_t nsteps, int ndim, double scale, double *out)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps * ndim; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = i / ndim;
         const int a = (int)(i % ndim);
-        out[i] = (mom[3 * (s + 1) + a] + mom[3 * s + a]) * scale;
+        double m1 = 0.0, m0 = 0.0;
+        for (int k = 0; k < nslots; ++k) {
+            m1 += part[((s + 1) * nslots + k) * 3 + a];
+            m0 += part[(s * nslots + k) * 3 + a];
+        }
+        out[i] = (m1 + m0) * scale;
     }
 }
 
@@ -247,12 +252,13 @@ hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const
 #undef CALL
 }
 
-hipError_t launch_ebar_grad(const double *mom, int64_t nsteps, int ndim, double scale, double *out, hipStream_t st)
+hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int ndim, double scale, double *out,
+                            hipStream_t st)
 {
     if (nsteps <= 0) return hipSuccess;
     const int64_t n = nsteps * ndim;
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_ebar_grad, dim3(blocks), dim3(256), 0, st, mom, nsteps, ndim, scale, out);
+    hipLaunchKernelGGL(k_ebar_grad, dim3(blocks), dim3(256), 0, st, part, nslots, nsteps, ndim, scale, out);
     return hipGetLastError();
 }
 

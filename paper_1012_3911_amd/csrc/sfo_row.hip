@@ -1,4 +1,6 @@
 // Instantiations of the row (x) pass for complex64 and complex128.
+#include <type_traits>
+
 #include "pass_kernels.h"
 
 namespace sfo {
@@ -40,6 +42,36 @@ template <typename R> bool xpass_variant_ok(int variant, int N)
     }
 }
 
+template <typename R, int N, size_t... I> int row_groups_n(int v, int64_t nrows, std::index_sequence<I...>)
+{
+    int g = -1;
+    auto one = [&](auto vi) {
+        constexpr int V = decltype(vi)::value;
+        if constexpr (row_variant_ok<R, N, V>()) {
+            constexpr RowVariant rv = kRowVariants[V];
+            using Tl = RowTile<N, rv.rad, rv.threads>;
+            if (nrows % Tl::ROWS) g = (int)nrows;
+            else if (rv.pipe > 1) g = (int)((nrows / Tl::ROWS + rv.pipe - 1) / rv.pipe);
+            else g = (int)(nrows / Tl::ROWS);
+        }
+    };
+    ((v == (int)I ? (one(std::integral_constant<int, (int)I>{}), 0) : 0), ...);
+    return g;
+}
+
+template <typename R> int xpass_groups(int variant, int N, int64_t nrows)
+{
+    if (variant < 0 || variant >= kNumRowVariants) return -1;
+    switch (N) {
+#define CASE(n) case n: return row_groups_n<R, n>(variant, nrows, std::make_index_sequence<kNumRowVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return -1;
+    }
+}
+
+template int xpass_groups<float>(int, int, int64_t);
+template int xpass_groups<double>(int, int, int64_t);
 template bool xpass_variant_ok<float>(int, int);
 template bool xpass_variant_ok<double>(int, int);
 
