@@ -51,7 +51,6 @@ MEASURED_TRAFFIC = {
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
     "row/0": (24856, 32768), "row/1": (24846, 32768), "row/2": (24971, 32768), "row/3": (24858, 32768),
     "row/4": (38440, 65911), "row/5": (24800, 32768), "row/6": (24805, 32768), "row/7": (24801, 32768),
-    "row/8": (24858, 32768), "row/9": (24862, 32768), "row/10": (24992, 32768), "row/11": (24864, 32768),
     "column/0": (16797, 33003), "column/1": (16790, 32777), "column/2": (16790, 35454),
     "column/4": (16790, 32833), "column/5": (16788, 33046), "column/7": (16968, 33747),
     "column/8": (16786, 34473),
@@ -166,6 +165,7 @@ def bench_batch(reps=3):
         g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c64")
         g.set_potential(wl.V0)
         g.set_field(wl.ebar)
+        g.autotune(10)  # tuned once per shape; later grids of that shape reuse the plan
         grids.append(g)
     psis = [torch.from_numpy(wl.psi0).to("cuda").to(torch.complex64).contiguous() for wl in wls]
     gs = [torch.from_numpy(t).to("cuda").to(torch.complex64).contiguous() for t in targets]

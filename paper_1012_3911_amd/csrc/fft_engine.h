@@ -236,22 +236,34 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// LDS placement of element p of a line during an exchange.  Bank conflicts
-// of the Stockham write pattern (stride L r between lanes) are removed by an
-// XOR swizzle of the low address bits for lines a work-group owns alone
-// (RowMap: the map stays inside aligned blocks of 32 and is a bijection, so a
-// line needs exactly N slots) and by one pad slot every 8 elements for
-// lines interleaved C-wise (ColMap: lane c of a column group is at offset c).
-// The swizzle shifts were chosen with a 64-bank, 4-byte-word model of the
-// LDS over the write and read patterns of every stage for N = 256..4096.
-template <typename R, int RAD> struct RowMap {
-    static constexpr int SH = RAD == 8 ? 3 : 4;
+// LDS placement of element p of a line during an exchange.  Two kinds:
+//
+// Padded maps, at(p) = (p + (p >> SH)) * C (one pad slot every 2^SH
+// elements; C lines interleaved, lane c at offset c).  Every Stockham access
+// pattern then splits into a per-thread base and compile-time offsets:
+// positions base + d with d = m L (writes: base = j0 L r + k, k < L, L and r
+// powers of two) or d = m T (reads: base = t < T) satisfy
+//     at(base + d) = at(base) + off(d),  off(d) = (d + (d >> SH)) * C,
+// because either d is a multiple of 2^SH, or the base's low part plus d stays
+// inside one block of 2^SH (L divides 2^SH and k < L).  The offsets become
+// immediate fields of the LDS instructions: no address arithmetic per element.
+//
+// The XOR map (the default for radix-8 rows) permutes the low address bits
+// inside aligned blocks of 32 and needs an address per element; its bank
+// conflicts are lower for that shape.  The shifts were chosen with a 64-bank, 4-byte-word model of
+// the LDS over the write and read patterns of every stage for N = 256..4096.
+template <typename R, int RAD, bool PAD = (RAD == 16)> struct RowMap {
+    static constexpr bool AFFINE = PAD;
+    static constexpr int SH = AFFINE ? (sizeof(R) == 4 ? 5 : 4) : 3;
     static constexpr int MASK = sizeof(R) == 4 ? 31 : 15;
-    __device__ static int at(int p) { return p ^ ((p >> SH) & MASK); }
-    static constexpr int slots(int N) { return N; }
+    __device__ static int at(int p) { return AFFINE ? p + (p >> SH) : p ^ ((p >> SH) & MASK); }
+    __host__ __device__ static constexpr int off(int d) { return d + (d >> SH); }
+    static constexpr int slots(int N) { return AFFINE ? N + (N >> SH) : N; }
 };
 template <int C> struct ColMap {
+    static constexpr bool AFFINE = true;
     __device__ static int at(int p) { return (p + (p >> 3)) * C; }
+    __host__ __device__ static constexpr int off(int d) { return (d + (d >> 3)) * C; }
     static constexpr int slots(int N) { return (N + N / 8) * C; }
 };
 
@@ -314,16 +326,28 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
             for (int m = 0; m < r; ++m) v[i + m * NB] = u[m];
         } else {
             const int base = (b / L) * (L * r) + k;
+            if constexpr (MAP::AFFINE) {
+                cx<R> *w = sh + MAP::at(base);
 #pragma unroll
-            for (int m = 0; m < r; ++m) sh[MAP::at(base + m * L)] = u[m];
+                for (int m = 0; m < r; ++m) w[MAP::off(m * L)] = u[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < r; ++m) sh[MAP::at(base + m * L)] = u[m];
+            }
         }
     }
     }
     if constexpr (!last) {
         __syncthreads();
         if (act) {
+            if constexpr (MAP::AFFINE) {
+                const cx<R> *q = sh + MAP::at(t);
 #pragma unroll
-            for (int m = 0; m < RV; ++m) v[m] = sh[MAP::at(t + m * T)];
+                for (int m = 0; m < RV; ++m) v[m] = q[MAP::off(m * T)];
+            } else {
+#pragma unroll
+                for (int m = 0; m < RV; ++m) v[m] = sh[MAP::at(t + m * T)];
+            }
         }
         __syncthreads();
     }

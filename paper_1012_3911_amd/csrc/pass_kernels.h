@@ -160,25 +160,15 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
     for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
 }
 
-// This row's dL/dV0 accumulator values (zero when the boundary starts the sum).
-template <typename R, int N, int RAD, int NV>
-__device__ __forceinline__ void row_load_acc(double (&accv)[NV], const GradArgs &ga, int64_t row, int t)
-{
-    static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
-    constexpr int T = LineShape<N, RAD>::T;
-#pragma unroll
-    for (int m = 0; m < NV; ++m) accv[m] = (ga.acc && !ga.acc_init) ? ga.acc[row * N + t + m * T] : 0.0;
-}
-
 // The register part of a row tile: inverse x-transform, potential factor,
 // gradient partials (mom accumulates this row's moments), forward
 // x-transform.  sh: this row's LDS exchange region; tw: twiddle table
 // (global or an LDS copy).
-template <typename R, int N, int RAD, int NS, int NV>
+template <typename R, int N, int RAD, int NS, bool PAD, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
-                                         const VStore<R> (&vv)[NV], const double (&accv)[NV], int64_t row, int ny,
-                                         cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph,
-                                         const GradArgs &ga, int mode, double (&mom)[3])
+                                         const VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh, int t,
+                                         const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
+                                         int mode, double (&mom)[3])
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     // everything below is derived from an opaque copy of t: in a persistent
@@ -187,7 +177,7 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     __asm__ __volatile__("" : "+v"(t));
     using Sh = LineShape<N, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV;
-    using Map = RowMap<R, RAD>;
+    using Map = RowMap<R, RAD, PAD>;
     if (mode & M_INV)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
@@ -270,7 +260,10 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
             const int x = t + m * T;
             const cx<R> ps = v[0][m], gq = v[NS - 1][m];
             const double b = (double)gq.re * (double)ps.im - (double)gq.im * (double)ps.re;
-            if (ga.acc) ga.acc[row * N + x] = accv[m] + ga.wacc * b;
+            if (ga.acc) {
+                double *ap = ga.acc + row * N + x;
+                *ap = (ga.acc_init ? 0.0 : *ap) + ga.wacc * b;
+            }
             sb += b;
             mom[0] += (ph.xmin[0] + (double)x * ph.dx[0]) * b;
         }
@@ -282,7 +275,7 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
 }
 
-template <typename R, int N, int RAD, int ROWS, int NS>
+template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16)>
 __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, int ny, const VStore<R> *__restrict__ V0,
                                          const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
                                          int mode, cx<R> *lds, double (*red)[3], int tid)
@@ -291,79 +284,29 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     constexpr int T = Sh::T, RV = Sh::RV;
     const int line = tid / T, t = tid % T;
     const int64_t row = row0 + line;
-    cx<R> *sh = lds + line * RowMap<R, RAD>::slots(N);
+    cx<R> *sh = lds + line * RowMap<R, RAD, PAD>::slots(N);
     cx<R> v[NS][RV];
     VStore<R> vv[RV];
-    double accv[RV];
     row_load<R, N, RAD, NS>(v, S, row, t);
-    // the potential (and accumulator) loads complete under the inverse transform
+    // the potential loads complete under the inverse transform
     if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
-    if (NS == 2 && (mode & M_GRAD)) row_load_acc<R, N, RAD>(accv, ga, row, t);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS>(v, vv, accv, row, ny, sh, t, tw, ph, ga, mode, mom);
+    row_body<R, N, RAD, NS, PAD>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom);
     row_store<R, N, RAD, NS>(v, S, row, t);
     if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
-template <typename R, int N, int RAD, int THREADS, int WPE, int NS>
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS, bool PAD = (RAD == 16)>
 __global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
         PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
 {
     constexpr int ROWS = RowTile<N, RAD, THREADS>::ROWS;
     if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
-    __shared__ cx<R> lds[ROWS * RowMap<R, RAD>::slots(N)];
+    __shared__ cx<R> lds[ROWS * RowMap<R, RAD, PAD>::slots(N)];
     __shared__ double red[16][3];
-    row_tile<R, N, RAD, ROWS, NS>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red, threadIdx.x);
-}
-
-// Pipelined persistent row pass: work-group b takes tiles b, b + G, ...
-// (PIPE of them, G = gridDim.x).  The next tile's state is loaded into
-// registers while the current one is transformed, so its HBM traffic
-// overlaps arithmetic.  The twiddle table is staged in LDS once per group:
-// a vector-memory load issued inside the transform would have to wait for
-// the prefetch before it (loads complete in issue order).
-template <typename R, int N, int RAD, int THREADS, int WPE, int NS, int PIPE>
-__global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_xpass_pipe(StatePtrs<R> S, int ny, int64_t ntiles, const VStore<R> *__restrict__ V0,
-             const TwEntry<R> *__restrict__ tw, PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
-{
-    if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
-    using Sh = LineShape<N, RAD>;
-    using Tl = RowTile<N, RAD, THREADS>;
-    constexpr int T = Sh::T, RV = Sh::RV, ROWS = Tl::ROWS;
-    constexpr int TWN = Sh::TW_SIZE > 0 ? Sh::TW_SIZE : 1;
-    __shared__ cx<R> lds[ROWS * RowMap<R, RAD>::slots(N)];
-    __shared__ TwEntry<R> twl[TWN];
-    __shared__ double red[16][3];
-    const int tid = threadIdx.x, line = tid / T, t = tid % T;
-    for (int i = tid; i < Sh::TW_SIZE; i += Tl::NT) twl[i] = tw[i];
-    cx<R> *sh = lds + line * RowMap<R, RAD>::slots(N);
-    const int64_t G = gridDim.x;
-    int64_t tile = blockIdx.x;
-    cx<R> v[NS][RV];
-    if (tile < ntiles) row_load<R, N, RAD, NS>(v, S, tile * ROWS + line, t);
-    __syncthreads();
-    double mom[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int i = 0; i < PIPE && tile < ntiles; ++i, tile += G) {
-        const int64_t row = tile * ROWS + line;
-        VStore<R> vv[RV];
-        double accv[RV];
-        if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
-        if (NS == 2 && (mode & M_GRAD)) row_load_acc<R, N, RAD>(accv, ga, row, t);
-        const bool more = i + 1 < PIPE && tile + G < ntiles;
-        cx<R> vn[NS][RV];
-        if (more) row_load<R, N, RAD, NS>(vn, S, (tile + G) * ROWS + line, t);
-        row_body<R, N, RAD, NS>(v, vv, accv, row, ny, sh, t, twl, ph, ga, mode, mom);
-        row_store<R, N, RAD, NS>(v, S, row, t);
-        if (more)
-#pragma unroll
-            for (int q = 0; q < NS; ++q)
-#pragma unroll
-                for (int m = 0; m < RV; ++m) v[q][m] = vn[q][m];
-    }
-    if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
+    row_tile<R, N, RAD, ROWS, NS, PAD>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red,
+                                       threadIdx.x);
 }
 
 // ------------------------------------------------------------ column pass --
@@ -619,9 +562,8 @@ template <typename R, int N, int V> constexpr bool row_variant_ok()
     constexpr RowVariant rv = kRowVariants[V];
     using Tl = RowTile<N, rv.rad, rv.threads>;
     if (N < 256 && V != 0) return false;  // short rows: default shape only
-    const int tw = rv.pipe > 1 ? LineShape<N, rv.rad>::TW_SIZE * (int)sizeof(TwEntry<R>) : 0;
     // 1 KiB stays free for the reduction buffer and static LDS of the kernel
-    return Tl::NT <= 1024 && Tl::ROWS * RowMap<R, rv.rad>::slots(N) * (int)sizeof(cx<R>) + tw <= 159 * 1024;
+    return Tl::NT <= 1024 && Tl::ROWS * RowMap<R, rv.rad, rv.pad>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024;
 }
 
 template <typename R, int N, int V, int NS>
@@ -637,17 +579,11 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
         using Tl = RowTile<N, rv.rad, rv.threads>;
         if (nrows % Tl::ROWS) {
             // fewer rows than a work-group holds (a single 1-D line): one row per group
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS>),
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS, rv.pad>),
                                dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), 0, st, S, ny,
                                (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
-        } else if constexpr (rv.pipe > 1) {
-            const int64_t ntiles = nrows / Tl::ROWS;
-            const int64_t groups = (ntiles + rv.pipe - 1) / rv.pipe;
-            hipLaunchKernelGGL((k_xpass_pipe<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pipe>),
-                               dim3((unsigned)groups, (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny, ntiles,
-                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         } else {
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS>),
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad>),
                                dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny,
                                (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         }

@@ -61,6 +61,8 @@ struct sfo_grid_s {
     double v0max = 0.0;   // max |V0|, for the bound of the potential phase
     int row_var = 0;      // tile variants chosen for the x pass and the y/z passes
     int col_var[3] = {0, 0, 0};
+    int row_var2 = -1;    // the same for the two-state passes of the reverse sweep (-1: as above)
+    int col_var2[3] = {-1, -1, -1};
     std::vector<double> ebar;  // host copy, nsteps x ndim
     double *ebar_d = nullptr;  // device copy, nsteps x ndim (the 1-D and batched kernels read it)
     int64_t ebar_steps = 0;
@@ -82,6 +84,10 @@ struct sfo_grid_s {
 };
 
 namespace {
+
+// Tile shape of the row pass / axis-ax pass for ns states (ns = 2: reverse sweep).
+int row_shape(const sfo_grid g, int ns) { return ns == 2 && g->row_var2 >= 0 ? g->row_var2 : g->row_var; }
+int col_shape(const sfo_grid g, int ax, int ns) { return ns == 2 && g->col_var2[ax] >= 0 ? g->col_var2[ax] : g->col_var[ax]; }
 
 void prof_clear(sfo_grid g)
 {
@@ -252,7 +258,7 @@ template <typename F> hipError_t timed(sfo_grid g, int kind, F &&fn)
 // Field integral of step s along axis a (zero without a table).
 double ebar_at(const sfo_grid g, int64_t s, int a)
 {
-    if (g->ebar_steps == 0) return 0.0;
+    if (s < 0 || s >= g->ebar_steps) return 0.0;  // callers check step ranges; timing runs may not
     return g->ebar[(size_t)(s * g->ndim + a)];
 }
 
@@ -291,7 +297,7 @@ sfo_status schro_xpass(sfo_grid g, void *psi, void *adj, int64_t sa, int64_t sb,
     const PhaseArgs ph = phase_args(g, sa, sb, sgn);
     const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
     HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
-        return launch_xpass<R>(g->row_var, (int)g->n[0], adj ? 2 : 1, S, g->n[1] * g->n[2], (int)g->n[1], g->V0,
+        return launch_xpass<R>(row_shape(g, adj ? 2 : 1), (int)g->n[0], adj ? 2 : 1, S, g->n[1] * g->n[2], (int)g->n[1], g->V0,
                                (const void *const *)g->tw[0], ph, ga, mode, g->st);
     }));
     return SFO_OK;
@@ -309,7 +315,7 @@ template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, void *ad
     if (g->ndim == 2) {
         KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
         HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-            return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, 1, 0, tw1, k, mode, g->st);
+            return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, 1, 0, tw1, k, mode, g->st);
         }));
     } else {
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
@@ -317,15 +323,15 @@ template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, void *ad
         KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
+                return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
                                          g->st);
             }));
         HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
-            return launch_colpass<R>(g->col_var[2], (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, mode, g->st);
+            return launch_colpass<R>(col_shape(g, 2, ns), (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, mode, g->st);
         }));
         if (mode & M_INV)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-                return launch_colpass<R>(g->col_var[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_INV,
+                return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_INV,
                                          g->st);
             }));
     }
@@ -478,6 +484,39 @@ double time_col(sfo_grid g, int ax, int v, cx<R> *psi, hipEvent_t ea, hipEvent_t
     });
 }
 
+// The reverse sweep's row pass (two states, gradient partials) and axis-ax
+// pass (two states) on scratch buffers.
+template <typename R>
+double time_row2(sfo_grid g, int v, cx<R> *psi, cx<R> *adj, double *acc, double *part, hipEvent_t ea, hipEvent_t eb,
+                 int reps)
+{
+    const PhaseArgs ph = phase_args(g, -1, 0, -1);
+    GradArgs ga{};
+    ga.acc = acc;
+    ga.wacc = 1.0;
+    ga.part = part;
+    return time_launches(g, ea, eb, reps, [&] {
+        return launch_xpass<R>(v, (int)g->n[0], 2, StatePtrs<R>{{psi, adj}}, g->n[1] * g->n[2], (int)g->n[1], g->V0,
+                               (const void *const *)g->tw[0], ph, ga, M_INV | M_PHASE | M_GRAD | M_FWD, g->st);
+    });
+}
+
+template <typename R>
+double time_col2(sfo_grid g, int ax, int v, cx<R> *psi, cx<R> *adj, hipEvent_t ea, hipEvent_t eb, int reps)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncols = ax == 1 ? nx : nx * ny;
+    const int nslab = (ax == 1 && g->ndim == 3) ? (int)nz : 1;
+    const bool kinetic = ax == g->ndim - 1;
+    const KinArgs k{g->kin[0], ax == 2 ? g->kin[1] : g->one, g->kin[ax], (int)nx, -1};
+    const KinArgs none{g->one, g->one, g->one, 1, -1};
+    return time_launches(g, ea, eb, reps, [&] {
+        return launch_colpass<R>(v, (int)g->n[ax], 2, StatePtrs<R>{{psi, adj}}, ncols, ncols, nslab, nx * ny,
+                                 (const void *const *)g->tw[ax], kinetic ? k : none,
+                                 kinetic ? (M_FWD | M_KIN | M_INV) : M_FWD, g->st);
+    });
+}
+
 // Scratch state and an event pair for the timing helpers.
 struct TimingScratch {
     void *mem = nullptr;
@@ -531,6 +570,36 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
             if (ms >= 0 && ms < best) { best = ms; g->col_var[ax] = v; }
         }
     }
+    if (g->d.equation != SFO_SCHRODINGER) return SFO_OK;
+    // the reverse sweep's two-state passes, on a second state, an accumulator and partial slots
+    const int64_t nrows = g->n[1] * g->n[2];
+    const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
+    void *extra = nullptr;
+    HIP_TRY(hipMalloc(&extra, sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows)));
+    hipError_t he = hipMemsetAsync(extra, 0, sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows), g->st);
+    cx<R> *adj = (cx<R> *)extra;
+    double *acc = (double *)((char *)extra + sbytes);
+    double *part = acc + g->ntot;
+    if (he == hipSuccess) {
+        best = 1e30;
+        for (int v = 0; v < kNumRowVariants; ++v) {
+            if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
+            const double ms = best_of([&] { return time_row2<R>(g, v, psi, adj, acc, part, ts.a, ts.b, reps); });
+            if (ms >= 0 && ms < best) { best = ms; g->row_var2 = v; }
+        }
+        for (int ax = 1; ax < g->ndim; ++ax) {
+            const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
+            best = 1e30;
+            for (int v = 0; v < kNumColVariants; ++v) {
+                if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+                const double ms = best_of([&] { return time_col2<R>(g, ax, v, psi, adj, ts.a, ts.b, reps); });
+                if (ms >= 0 && ms < best) { best = ms; g->col_var2[ax] = v; }
+            }
+        }
+        he = hipStreamSynchronize(g->st);
+    }
+    (void)hipFree(extra);
+    if (he != hipSuccess) return fail(SFO_E_HIP, "autotune (reverse sweep): %s", hipGetErrorString(he));
     return SFO_OK;
 }
 
@@ -571,7 +640,7 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
 {
     // moment partials: boundary n (0..nsteps) x slot x 3; the 1-D kernel writes one slot per boundary
     const int64_t nrows = g->n[1] * g->n[2];
-    const int nslots = g->ndim == 1 ? 1 : xpass_groups<R>(g->row_var, (int)g->n[0], nrows);
+    const int nslots = g->ndim == 1 ? 1 : xpass_groups<R>(row_shape(g, 2), (int)g->n[0], nrows);
     if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
     const int64_t need = 3 * (int64_t)nslots * (nsteps + 1);
     if (g->part_cap < need) {
@@ -804,7 +873,7 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
         if (g->ndim == 2) {
             for (const auto &G : b->groups)
                 if (G.ndim == 2 && G.nx == q.nx && G.ny == q.ny)
-                    q.gslots = std::max(1, xpass_groups<R>(G.rep->row_var, q.nx, q.ny));
+                    q.gslots = std::max(1, xpass_groups<R>(row_shape(G.rep, 2), q.nx, q.ny));
         }
         if (gadj) {
             q.gadj = (cx<R> *)gadj[i];
@@ -861,7 +930,7 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
             if (e != hipSuccess || G.ndim != 2) continue;
             PhaseArgs ph{};
             ph.sgn = dir;
-            e = launch_xpass<R>(G.rep->row_var, G.nx, ns, none, G.ny, G.ny, nullptr, (const void *const *)G.rep->tw[0],
+            e = launch_xpass<R>(row_shape(G.rep, ns), G.nx, ns, none, G.ny, G.ny, nullptr, (const void *const *)G.rep->tw[0],
                                 ph, GradArgs{}, mode, s, grp_of(G, sa, sb, jmom, wmul, init), G.count);
         }
     };
@@ -869,7 +938,7 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
         for (const auto &G : b->groups) {
             if (e != hipSuccess || G.ndim != 2) continue;
             KinArgs k{nullptr, nullptr, nullptr, 1, dir};
-            e = launch_colpass<R>(G.rep->col_var[1], G.ny, ns, none, G.nx, G.nx, 1, 0,
+            e = launch_colpass<R>(col_shape(G.rep, 1, ns), G.ny, ns, none, G.nx, G.nx, 1, 0,
                                   (const void *const *)G.rep->tw[1], k, M_FWD | M_KIN | M_INV, s,
                                   grp_of(G, -1, -1, 0, 1.0, 0), G.count);
         }
@@ -1162,10 +1231,17 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps)
         auto it = g_plans.find(key);
         if (it != g_plans.end()) {
             const int p[3] = {it->second[0], it->second[1], it->second[2]};
-            if (g->c128 ? plan_valid<double>(g, p) : plan_valid<float>(g, p)) {
+            auto r = g_plans.find(key + ":reverse");
+            const int q[3] = {r != g_plans.end() ? r->second[0] : p[0], r != g_plans.end() ? r->second[1] : p[1],
+                              r != g_plans.end() ? r->second[2] : p[2]};
+            if ((g->c128 ? plan_valid<double>(g, p) : plan_valid<float>(g, p)) &&
+                (g->c128 ? plan_valid<double>(g, q) : plan_valid<float>(g, q))) {
                 g->row_var = p[0];
                 g->col_var[1] = p[1];
                 g->col_var[2] = p[2];
+                g->row_var2 = q[0];
+                g->col_var2[1] = q[1];
+                g->col_var2[2] = q[2];
                 return SFO_OK;
             }
         }
@@ -1175,6 +1251,7 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps)
     if (s) return s;
     std::lock_guard<std::mutex> lk(g_plan_mu);
     store_plan(key, {g->row_var, g->col_var[1], g->col_var[2]});
+    store_plan(key + ":reverse", {row_shape(g, 2), col_shape(g, 1, 2), col_shape(g, 2, 2)});
     return SFO_OK;
 }
 
@@ -1207,6 +1284,8 @@ sfo_status sfo_set_plan(sfo_grid g, const int32_t *plan)
     g->row_var = p[0];
     g->col_var[1] = p[1];
     g->col_var[2] = p[2];
+    g->row_var2 = -1;  // the reverse sweep follows the forced shapes
+    g->col_var2[1] = g->col_var2[2] = -1;
     return SFO_OK;
 }
 

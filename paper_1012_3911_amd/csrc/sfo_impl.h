@@ -121,14 +121,16 @@ template <typename R> struct GroupArgs {
 // minimum waves per SIMD the register allocation must allow.  Column
 // passes: register radix, adjacent lines per work-group, waves per SIMD.
 struct RowVariant {
-    int rad, threads, wpe, pipe;  // pipe > 1: persistent, pipe tiles per group, prefetching
+    int rad, threads, wpe;
+    bool pad;  // padded LDS map with immediate offsets (else the XOR swizzle)
 };
 struct ColVariant {
     int rad, cols, wpe;
 };
-constexpr RowVariant kRowVariants[] = {{16, 256, 1, 1}, {16, 128, 1, 1}, {16, 512, 1, 1}, {16, 256, 3, 1},
-                                       {16, 256, 4, 1}, {8, 256, 1, 1},  {8, 512, 1, 1},  {8, 256, 4, 1},
-                                       {16, 256, 1, 2}, {16, 512, 1, 2}, {16, 128, 1, 2}, {16, 256, 1, 4}};
+constexpr RowVariant kRowVariants[] = {{16, 256, 1, true}, {16, 128, 1, true}, {16, 512, 1, true},
+                                       {16, 256, 3, true}, {16, 256, 4, true}, {8, 256, 1, false},
+                                       {8, 512, 1, false}, {8, 256, 4, false}, {8, 256, 1, true},
+                                       {8, 512, 1, true}};
 constexpr ColVariant kColVariants[] = {{16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2},
                                        {16, 2, 4}, {8, 8, 1},  {8, 4, 1},  {8, 2, 4}};
 constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);

@@ -50,9 +50,7 @@ template <typename R, int N, size_t... I> int row_groups_n(int v, int64_t nrows,
         if constexpr (row_variant_ok<R, N, V>()) {
             constexpr RowVariant rv = kRowVariants[V];
             using Tl = RowTile<N, rv.rad, rv.threads>;
-            if (nrows % Tl::ROWS) g = (int)nrows;
-            else if (rv.pipe > 1) g = (int)((nrows / Tl::ROWS + rv.pipe - 1) / rv.pipe);
-            else g = (int)(nrows / Tl::ROWS);
+            g = (int)(nrows % Tl::ROWS ? nrows : nrows / Tl::ROWS);
         }
     };
     ((v == (int)I ? (one(std::integral_constant<int, (int)I>{}), 0) : 0), ...);

@@ -139,3 +139,26 @@ def test_autograd_control_gradient(orc, dtype):
     gv = V0.grad.cpu().numpy()
     assert np.linalg.norm(gv - dV) / np.linalg.norm(dV) < tol
     grid.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_after_autotune(orc, dtype):
+    """The autotuner picks the reverse sweep's two-state shapes separately from
+    the forward ones; the gradient must not depend on that choice."""
+    import torch
+
+    wl, target = problem(2, n=(256, 128))
+    psiT, gT, g0, dE, dV = oracle_grads(orc, wl, target)
+    if dtype == "c64":
+        psiT = psiT.astype(np.complex64).astype(np.complex128)
+    g = make_grid(wl, dtype)
+    g.autotune(2)
+    psi = to_device(psiT, dtype)
+    gv = to_device(gT, dtype)
+    gdE, gdV = g.adjoint(psi, gv, 0, wl.nsteps)
+    torch.cuda.synchronize()
+    tol = 1e-10 if dtype == "c128" else 1e-4
+    assert rel_l2(gv.cpu().numpy(), g0) < tol
+    assert np.linalg.norm(gdE.cpu().numpy() - dE) / np.linalg.norm(dE) < tol
+    assert np.linalg.norm((gdV.cpu().numpy() - dV).ravel()) / np.linalg.norm(dV.ravel()) < tol
+    g.close()
