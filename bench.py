@@ -193,6 +193,35 @@ def bench_batch(reps=3):
             "fwd_adjoint_updates_per_s": pts * S * reps / (t2 - t1)}
 
 
+def bench_beyond_mall(steps=40):
+    """2-D 4096 x 4096 complex128 (256 MiB of state, beyond the 256 MiB
+    Infinity Cache once the potential is counted): the passes stream from HBM."""
+    import torch
+    from paper_1012_3911_amd import sfo, workloads as W
+
+    wl = W.softcore_2d_laser(n=4096, nsteps=steps)
+    g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c128")
+    g.set_potential(wl.V0)
+    g.set_field(wl.ebar)
+    plan = g.autotune(5)
+    psi = torch.from_numpy(wl.psi0).to("cuda").to(torch.complex128).contiguous()
+    g.propagate(psi, 0, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.propagate(psi, 0, steps)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    kern = {name: g.time_pass(kind, 50) for name, kind in (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
+    g.close()
+    del psi
+    torch.cuda.empty_cache()
+    npts = wl.n[0] * wl.n[1]
+    alg = {"row": npts * (2 * 16 + 8), "column": npts * 2 * 16}
+    return {"grid": list(wl.n), "dtype": "c128", "ms_per_step": 1e3 * t, "updates_per_s": npts / t, "plan": list(plan),
+            "kernels": {k: {"avg_us": 1e3 * v, "gbs": alg[k] / (v * 1e-3) / 1e9,
+                            "frac": alg[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS} for k, v in kern.items()}}
+
+
 def copy_calibration():
     """A plain device copy of known size: the HBM counters of this kernel
     calibrate FETCH_SIZE / WRITE_SIZE of the split-step kernels."""
@@ -207,13 +236,16 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
-def cpu_baseline(wl, budget):
+def cpu_baseline(wl, budget, threads=None):
     """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
     import numpy as np
 
     import oracle
 
     oracle.build(force=False)
+    all_cores = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
     cores = oracle.num_threads()
     psi = wl.psi0.copy()
     steps = 0
@@ -225,6 +257,8 @@ def cpu_baseline(wl, budget):
         if el >= budget or steps >= wl.nsteps:
             break
     pts = int(np.prod(wl.n))
+    if threads:
+        oracle.set_num_threads(all_cores)
     return dict(value=pts * steps / el, unit="grid-point updates/s", cores=cores, kind="oracle",
                 sample="%d of %d steps of the same %dx%d workload, FP64 radix-2, OpenMP over lines, %.1f s"
                        % (steps, wl.nsteps, wl.n[0], wl.n[1], el))
@@ -331,8 +365,13 @@ def main():
         out["batch"] = bench_batch()
         print("# batch fwd %.2f ms/run, fwd+adjoint %.2f ms/run" % (out["batch"]["fwd_ms_per_run"],
               out["batch"]["fwd_adjoint_ms_per_run"]), file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["beyond_mall"] = bench_beyond_mall()
+        print("# 4096^2 c128 %.3f ms/step" % out["beyond_mall"]["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        one = cpu_baseline(wl, args.cpu_seconds, threads=1)
+        out["cpu_baseline_one_core"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
     print(json.dumps(out))
 
 

@@ -166,9 +166,9 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
 // (global or an LDS copy).
 template <typename R, int N, int RAD, int NS, bool PAD, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
-                                         const VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh, int t,
+                                         VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh, int t,
                                          const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
-                                         int mode, double (&mom)[3])
+                                         int mode, double (&mom)[3], const VStore<R> *__restrict__ V0late = nullptr)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     // everything below is derived from an opaque copy of t: in a persistent
@@ -181,6 +181,8 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     if (mode & M_INV)
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+    // potential loaded here rather than before the transform: fewer registers held through it
+    if (V0late && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0late, row, t);
     const int64_t y = row % ny, z = row / ny;
     if (mode & M_PHASE) {
         const double sg = (double)ph.sgn;
@@ -275,7 +277,7 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
 }
 
-template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16)>
+template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16), bool LATE = false>
 __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, int ny, const VStore<R> *__restrict__ V0,
                                          const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
                                          int mode, cx<R> *lds, double (*red)[3], int tid)
@@ -288,15 +290,15 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     cx<R> v[NS][RV];
     VStore<R> vv[RV];
     row_load<R, N, RAD, NS>(v, S, row, t);
-    // the potential loads complete under the inverse transform
-    if (mode & M_PHASE) row_load_v0<R, N, RAD>(vv, V0, row, t);
+    // the potential loads complete under the inverse transform (or, LATE, are issued after it)
+    if (!LATE && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0, row, t);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS, PAD>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom);
+    row_body<R, N, RAD, NS, PAD>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom, LATE ? V0 : nullptr);
     row_store<R, N, RAD, NS>(v, S, row, t);
     if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
-template <typename R, int N, int RAD, int THREADS, int WPE, int NS, bool PAD = (RAD == 16)>
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS, bool PAD = (RAD == 16), bool LATE = false>
 __global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
         PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
@@ -305,8 +307,8 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
     if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
     __shared__ cx<R> lds[ROWS * RowMap<R, RAD, PAD>::slots(N)];
     __shared__ double red[16][3];
-    row_tile<R, N, RAD, ROWS, NS, PAD>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red,
-                                       threadIdx.x);
+    row_tile<R, N, RAD, ROWS, NS, PAD, LATE>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red,
+                                             threadIdx.x);
 }
 
 // ------------------------------------------------------------ column pass --
@@ -583,7 +585,7 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
                                dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), 0, st, S, ny,
                                (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         } else {
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad>),
+            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late>),
                                dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny,
                                (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         }

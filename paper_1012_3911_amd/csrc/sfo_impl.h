@@ -122,15 +122,17 @@ template <typename R> struct GroupArgs {
 // passes: register radix, adjacent lines per work-group, waves per SIMD.
 struct RowVariant {
     int rad, threads, wpe;
-    bool pad;  // padded LDS map with immediate offsets (else the XOR swizzle)
+    bool pad;   // padded LDS map with immediate offsets (else the XOR swizzle)
+    bool late;  // potential loaded after the inverse transform (fewer registers held)
 };
 struct ColVariant {
     int rad, cols, wpe;
 };
-constexpr RowVariant kRowVariants[] = {{16, 256, 1, true}, {16, 128, 1, true}, {16, 512, 1, true},
-                                       {16, 256, 3, true}, {16, 256, 4, true}, {8, 256, 1, false},
-                                       {8, 512, 1, false}, {8, 256, 4, false}, {8, 256, 1, true},
-                                       {8, 512, 1, true}};
+constexpr RowVariant kRowVariants[] = {
+    {16, 256, 1, true, false}, {16, 128, 1, true, false}, {16, 512, 1, true, false}, {16, 256, 3, true, false},
+    {16, 256, 4, true, false}, {8, 256, 1, false, false},  {8, 512, 1, false, false},  {8, 256, 4, false, false},
+    {8, 256, 1, true, false},  {8, 512, 1, true, false},  {16, 256, 4, true, true},  {16, 128, 4, true, true},
+    {16, 256, 1, true, true},  {8, 256, 1, false, true}};
 constexpr ColVariant kColVariants[] = {{16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2},
                                        {16, 2, 4}, {8, 8, 1},  {8, 4, 1},  {8, 2, 4}};
 constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);
