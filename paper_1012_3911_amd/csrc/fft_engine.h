@@ -30,6 +30,43 @@ struct __align__(2 * sizeof(R)) cx {
     R re, im;
 };
 
+// Global-memory access.  The state, potential and accumulator pointers of the
+// passes always address device memory, but pointers taken from argument
+// structures or batch descriptors reach the compiler as generic pointers,
+// which it accesses with flat instructions.  A flat access also counts
+// against the LDS wait counter, so each wait for an LDS exchange would wait
+// for outstanding loads as well, and it cannot take a scalar base address.
+// These accessors state the address space.
+template <typename R> struct Vec2T;
+template <> struct Vec2T<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <> struct Vec2T<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename R> __device__ __forceinline__ cx<R> gload(const cx<R> *p)
+{
+    typedef typename Vec2T<R>::type V;
+    const V v = *(const __attribute__((address_space(1))) V *)p;
+    return {v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void gstore(cx<R> *p, cx<R> a)
+{
+    typedef typename Vec2T<R>::type V;
+    V v;
+    v.x = a.re;
+    v.y = a.im;
+    *(__attribute__((address_space(1))) V *)p = v;
+}
+template <typename T> __device__ __forceinline__ T gload1(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T> __device__ __forceinline__ void gstore1(T *p, T a)
+{
+    *(__attribute__((address_space(1))) T *)p = a;
+}
+
 // Twiddle table entry: FP32 hi/lo pair for complex64, plain FP64 for complex128.
 template <typename R> struct TwEntry;
 template <> struct __align__(16) TwEntry<float> { float hr, hi, lr, li; };
@@ -67,16 +104,21 @@ __device__ __forceinline__ cx<double> cmul_d(cx<double> a, double wr, double wi)
     return {__builtin_fma(a.re, wr, -(a.im * wi)), __builtin_fma(a.re, wi, a.im * wr)};
 }
 
-// Table twiddle W_N^idx (forward table), conjugated for the inverse transform.
-template <int DIR> __device__ __forceinline__ cx<float> twiddle(cx<float> a, const TwEntry<float> *tw, int idx)
+// Table twiddle W_N^(c + k) (forward table), conjugated for the inverse
+// transform.  c is a compile-time entry index and kb = k * sizeof(TwEntry)
+// the thread's unsigned byte offset, so that the address is a uniform base
+// plus a 32-bit vector offset (no 64-bit vector arithmetic per load).
+template <int DIR>
+__device__ __forceinline__ cx<float> twiddle(cx<float> a, const TwEntry<float> *tw, int c, uint32_t kb)
 {
-    TwEntry<float> w = tw[idx];
+    TwEntry<float> w = *(const TwEntry<float> *)((const char *)(tw + c) + kb);
     if (DIR > 0) { w.hi = -w.hi; w.li = -w.li; }
     return cmul_hl(a, w.hr, w.hi, w.lr, w.li);
 }
-template <int DIR> __device__ __forceinline__ cx<double> twiddle(cx<double> a, const TwEntry<double> *tw, int idx)
+template <int DIR>
+__device__ __forceinline__ cx<double> twiddle(cx<double> a, const TwEntry<double> *tw, int c, uint32_t kb)
 {
-    TwEntry<double> w = tw[idx];
+    TwEntry<double> w = *(const TwEntry<double> *)((const char *)(tw + c) + kb);
     return cmul_d(a, w.r, DIR > 0 ? -w.i : w.i);
 }
 
@@ -213,12 +255,12 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
         // an opaque copy of the index pins this group's table loads here: the
         // table is read-only, and the compiler would otherwise issue every
         // load of the transform at its start and hold them all in registers
-        int kk = k;
-        __asm__ __volatile__("" : "+v"(kk));
+        uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TW);
+        __asm__ __volatile__("" : "+v"(kb));
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1) {
             const int j = N2 * j1 + j2;
-            a[j2][j1] = j == 0 ? v[0] : twiddle<DIR>(v[j], tw, two + (j - 1) * L + kk);
+            a[j2][j1] = j == 0 ? v[0] : twiddle<DIR>(v[j], tw, two + (j - 1) * L, kb);
         }
         dft<N1, DIR>(a[j2]);
     }
@@ -314,10 +356,11 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
             tw_dft<r, DIR>(u, tw, TWO, L, k);
         } else {
             if constexpr (L > 1) {
-                int kk = k;  // pins the table loads to this stage (see tw_dft)
-                __asm__ __volatile__("" : "+v"(kk));
+                // pins the table loads to this stage (see tw_dft)
+                uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TwEntry<R>);
+                __asm__ __volatile__("" : "+v"(kb));
 #pragma unroll
-                for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L + kk);
+                for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L, kb);
             }
             dft<r, DIR>(u);
         }

@@ -125,39 +125,61 @@ __device__ __forceinline__ void block_part3(double (&v)[3], double (*red)[3], do
 // M_GRAD (NS = 2) additionally forms b = Im(conj(g) psi) at this step
 // boundary in real space: acc += w b (the dL/dV0 accumulator) and the
 // moments sum_x (x b, y b, z b), summed over the work-group into ga.part.
+// Row tile addressing: the base of element m of the tile's first row is
+// uniform and is kept in scalar registers (an opaque copy stops the compiler
+// from folding it into a 64-bit vector address); a thread adds its own
+// 32-bit offset (line * N + t) * size.  Only for values uniform over the
+// work-group.
+template <typename P> __device__ __forceinline__ P scalar_base(P p)
+{
+    __asm__ __volatile__("" : "+s"(p));
+    return p;
+}
+
 template <typename R, int N, int RAD, int NS, int NV>
-__device__ __forceinline__ void row_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t row,
-                                         int t)
+__device__ __forceinline__ void row_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t row0,
+                                         uint32_t lt)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
+    const uint32_t tb = lt * (uint32_t)sizeof(cx<R>);
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][row * N + t + m * T];
+        for (int m = 0; m < RV; ++m) {
+            const char *b = scalar_base((const char *)(S.p[q] + row0 * N + m * T));
+            v[q][m] = gload((const cx<R> *)(b + tb));
+        }
 }
 
 template <typename R, int N, int RAD, int NS, int NV>
 __device__ __forceinline__ void row_store(const cx<R> (&v)[NS][NV], const StatePtrs<R> &S,
-                                          int64_t row, int t)
+                                          int64_t row0, uint32_t lt)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
+    const uint32_t tb = lt * (uint32_t)sizeof(cx<R>);
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) S.p[q][row * N + t + m * T] = v[q][m];
+        for (int m = 0; m < RV; ++m) {
+            char *b = scalar_base((char *)(S.p[q] + row0 * N + m * T));
+            gstore((cx<R> *)(b + tb), v[q][m]);
+        }
 }
 
 template <typename R, int N, int RAD, int NV>
 __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R> *__restrict__ V0,
-                                            int64_t row, int t)
+                                            int64_t row0, uint32_t lt)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
-    const VStore<R> *vr = V0 + row * N;
+    const uint32_t tb = lt * (uint32_t)sizeof(VStore<R>);
 #pragma unroll
-    for (int m = 0; m < RV; ++m) vv[m] = vr[t + m * T];
+    for (int m = 0; m < RV; ++m) {
+        const char *b = scalar_base((const char *)(V0 + row0 * N + m * T));
+        vv[m] = gload1((const VStore<R> *)(b + tb));
+    }
 }
 
 // The register part of a row tile: inverse x-transform, potential factor,
@@ -166,7 +188,7 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
 // (global or an LDS copy).
 template <typename R, int N, int RAD, int NS, bool PAD, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
-                                         VStore<R> (&vv)[NV], int64_t row, int ny, cx<R> *sh, int t,
+                                         VStore<R> (&vv)[NV], int64_t row0, int line, int ny, cx<R> *sh, int t,
                                          const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
                                          int mode, double (&mom)[3], const VStore<R> *__restrict__ V0late = nullptr)
 {
@@ -182,7 +204,9 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
 #pragma unroll
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
     // potential loaded here rather than before the transform: fewer registers held through it
-    if (V0late && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0late, row, t);
+    const int64_t row = row0 + line;
+    const uint32_t lt = (uint32_t)(line * N + t);
+    if (V0late && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0late, row0, lt);
     const int64_t y = row % ny, z = row / ny;
     if (mode & M_PHASE) {
         const double sg = (double)ph.sgn;
@@ -263,8 +287,8 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
             const cx<R> ps = v[0][m], gq = v[NS - 1][m];
             const double b = (double)gq.re * (double)ps.im - (double)gq.im * (double)ps.re;
             if (ga.acc) {
-                double *ap = ga.acc + row * N + x;
-                *ap = (ga.acc_init ? 0.0 : *ap) + ga.wacc * b;
+                double *ap = (double *)(scalar_base((char *)(ga.acc + row0 * N + m * T)) + lt * sizeof(double));
+                gstore1(ap, (ga.acc_init ? 0.0 : gload1(ap)) + ga.wacc * b);
             }
             sb += b;
             mom[0] += (ph.xmin[0] + (double)x * ph.dx[0]) * b;
@@ -285,16 +309,18 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     using Sh = LineShape<N, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV;
     const int line = tid / T, t = tid % T;
-    const int64_t row = row0 + line;
     cx<R> *sh = lds + line * RowMap<R, RAD, PAD>::slots(N);
     cx<R> v[NS][RV];
     VStore<R> vv[RV];
-    row_load<R, N, RAD, NS>(v, S, row, t);
+    uint32_t lt = (uint32_t)(line * N + t);
+    row_load<R, N, RAD, NS>(v, S, row0, lt);
     // the potential loads complete under the inverse transform (or, LATE, are issued after it)
-    if (!LATE && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0, row, t);
+    if (!LATE && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0, row0, lt);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS, PAD>(v, vv, row, ny, sh, t, tw, ph, ga, mode, mom, LATE ? V0 : nullptr);
-    row_store<R, N, RAD, NS>(v, S, row, t);
+    row_body<R, N, RAD, NS, PAD>(v, vv, row0, line, ny, sh, t, tw, ph, ga, mode, mom, LATE ? V0 : nullptr);
+    // the offset is recomputed rather than held through the transforms
+    __asm__ __volatile__("" : "+v"(lt));
+    row_store<R, N, RAD, NS>(v, S, row0, lt);
     if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
@@ -318,32 +344,46 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
 // Work-groups are dispatched round-robin over the 8 XCDs; the group index is
 // remapped so that consecutive column groups, which share cache lines, run
 // on the same XCD (and so share its L2) at about the same time.
+// Addresses: the work-group's base (slab, first line) and the distance
+// between a thread's elements are uniform and live in scalar registers; a
+// thread adds only its own 32-bit byte offset tb = (t stride + c) * size, so
+// each access is a scalar-base + vector-offset load or store with no 64-bit
+// vector arithmetic (the launcher checks that tb fits 32 bits).
 template <typename R, int N, int RAD, int NS, int NV>
-__device__ __forceinline__ void col_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t off,
-                                         int64_t stride, int t)
+__device__ __forceinline__ void col_load(cx<R> (&v)[NS][NV], const StatePtrs<R> &S, int64_t ubase,
+                                         int64_t stride, uint32_t tb)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+    for (int q = 0; q < NS; ++q) {
+        const char *b = (const char *)(S.p[q] + ubase);
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[q][m] = S.p[q][off + (int64_t)(t + m * T) * stride];
+        for (int m = 0; m < RV; ++m) {
+            // opaque scalar base: keeps the compiler from folding the uniform
+            // part into a 64-bit vector address
+            const char *bm = b + (int64_t)m * T * stride * (int64_t)sizeof(cx<R>);
+            __asm__ __volatile__("" : "+s"(bm));
+            v[q][m] = gload((const cx<R> *)(bm + tb));
+        }
+    }
 }
-
 template <typename R, int N, int RAD, int NS, int NV>
 __device__ __forceinline__ void col_store(const cx<R> (&v)[NS][NV], const StatePtrs<R> &S,
-                                          int64_t off, int64_t stride, int t)
+                                          int64_t ubase, int64_t stride, uint32_t tb)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
-    // strided addresses do not fit an immediate offset; recompute them here
-    // rather than holding the load addresses (two registers each) through
-    // the transforms
-    __asm__ __volatile__("" : "+v"(off), "+v"(t));
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+    for (int q = 0; q < NS; ++q) {
+        char *b = (char *)(S.p[q] + ubase);
 #pragma unroll
-        for (int m = 0; m < RV; ++m) S.p[q][off + (int64_t)(t + m * T) * stride] = v[q][m];
+        for (int m = 0; m < RV; ++m) {
+            char *bm = b + (int64_t)m * T * stride * (int64_t)sizeof(cx<R>);
+            __asm__ __volatile__("" : "+s"(bm));
+            gstore((cx<R> *)(bm + tb), v[q][m]);
+        }
+    }
 }
 
 // Forward transform, kinetic factor kc * kL[j] (kc: this line's factor from
@@ -363,12 +403,12 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
     if (mode & M_KIN) {
         // index laundered after the transform: the table loads stay here
         // instead of being hoisted above it (16 FP64 pairs held through it)
-        int tk = t;
+        uint32_t tk = (uint32_t)t * (uint32_t)sizeof(double2);
         __asm__ __volatile__("" : "+v"(tk));
 #pragma unroll
         for (int m = 0; m < RV; ++m) {
-            const double2 l = kL[tk + m * T];
-            const double kr = kcr * l.x - kci * l.y, ki = kcr * l.y + kci * l.x;
+            const cx<double> l = gload((const cx<double> *)((const char *)kL + m * T * (int)sizeof(double2) + tk));
+            const double kr = kcr * l.re - kci * l.im, ki = kcr * l.im + kci * l.re;
 #pragma unroll
             for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)sgn * ki);
             if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four points at a time
@@ -387,17 +427,21 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
     constexpr int RV = LineShape<N, RAD>::RV;
     const int c = tid % C, t = tid / C;
     const int64_t col = gx * C + c;
-    const int64_t off = slab * slab_stride + col;
+    const int64_t ubase = slab * slab_stride + gx * C;
+    uint32_t tb = ((uint32_t)t * (uint32_t)stride + (uint32_t)c) * (uint32_t)sizeof(cx<R>);
     cx<R> v[NS][RV];
-    col_load<R, N, RAD, NS>(v, S, off, stride, t);
+    col_load<R, N, RAD, NS>(v, S, ubase, stride, tb);
     double kcr = 1.0, kci = 0.0;
     if (mode & M_KIN) {
-        const double2 a = kin.kA[col % kin.nA], b = kin.kB[col / kin.nA];
-        kcr = a.x * b.x - a.y * b.y;
-        kci = a.x * b.y + a.y * b.x;
+        const cx<double> a = gload((const cx<double> *)kin.kA + col % kin.nA),
+                         b = gload((const cx<double> *)kin.kB + col / kin.nA);
+        kcr = a.re * b.re - a.im * b.im;
+        kci = a.re * b.im + a.im * b.re;
     }
     col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode);
-    col_store<R, N, RAD, NS>(v, S, off, stride, t);
+    // the offset is recomputed rather than held through the transforms
+    __asm__ __volatile__("" : "+v"(tb));
+    col_store<R, N, RAD, NS>(v, S, ubase, stride, tb);
 }
 
 template <typename R, int N, int RAD, int C, int WPE, int NS>
@@ -623,6 +667,9 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
         constexpr ColVariant cv = kColVariants[V];
         const void *tw = tws[cv.rad == 8 ? 0 : 1];
         if (ncols % cv.cols) return hipErrorInvalidValue;
+        // per-thread byte offsets within a work-group's lines are 32-bit
+        if (((int64_t)(LineShape<N, cv.rad>::T - 1) * stride + cv.cols) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>),
                            dim3((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup),
                            dim3(cv.cols * LineShape<N, cv.rad>::T), 0, st, S, stride, slab_stride,
