@@ -13,15 +13,21 @@
 // through LDS, so a forward transform, a point-wise factor and an inverse
 // transform chain with no exchange between them.
 //
-// Precision.  Twiddles come from FP64 tables.  For complex64 each twiddle is
-// stored as an FP32 hi/lo pair and applied with FMAs, and the internal
-// constants of the radix-8/16 codelets likewise, so that the rounded
-// twiddle's modulus error (about 3e-8 for angles near 45 degrees, the same
-// for every step) does not turn into a systematic norm drift; what remains
-// is the rounding of each arithmetic result, which is not systematic.
+// Precision.  Twiddles come from FP64 tables.  For complex64 a stage reads
+// only W^k of each butterfly (stored as an FP32 hi/lo pair, exact to about
+// 2^-48) and forms the other factors W^{jk} from it in FP64 by a few
+// products; each factor is applied in FP64 and rounded to FP32 once.  The
+// internal constants of the radix-8/16 codelets are FP32 hi/lo pairs applied
+// with FMAs.  Either way the rounded twiddle's modulus error (about 3e-8 for
+// angles near 45 degrees in plain FP32, the same for every step) does not
+// turn into a systematic norm drift; what remains is the rounding of each
+// arithmetic result, which is not systematic.  Complex128 reads every factor
+// from its FP64 table.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace sfo {
 
@@ -120,6 +126,30 @@ __device__ __forceinline__ cx<double> twiddle(cx<double> a, const TwEntry<double
 {
     TwEntry<double> w = *(const TwEntry<double> *)((const char *)(tw + c) + kb);
     return cmul_d(a, w.r, DIR > 0 ? -w.i : w.i);
+}
+
+// W_N^(c + k) of the forward table in FP64 (complex64 entries: hi + lo).
+__device__ __forceinline__ void twiddle_base(const TwEntry<float> *tw, int c, uint32_t kb, double &wr, double &wi)
+{
+    const TwEntry<float> e = *(const TwEntry<float> *)((const char *)(tw + c) + kb);
+    wr = (double)e.hr + (double)e.lr;
+    wi = (double)e.hi + (double)e.li;
+}
+
+// (a + i b) (c + i d) in FP64.
+__device__ __forceinline__ void cmul64(double &a, double &b, double c, double d)
+{
+    const double r = a * c - b * d;
+    b = a * d + b * c;
+    a = r;
+}
+
+// v * (c + i s) in FP64, rounded once.
+__device__ __forceinline__ cx<float> mul_round(cx<float> v, double c, double s)
+{
+    const double re = (double)v.re * c - (double)v.im * s;
+    const double im = (double)v.re * s + (double)v.im * c;
+    return {(float)re, (float)im};
 }
 
 // cos(2 pi k / 16), k = 0..15 (FP64 constants of the radix-8/16 codelets).
@@ -250,6 +280,32 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
 {
     constexpr int N1 = 4, N2 = NR / 4;
     cx<R> a[N2][N1];
+    if constexpr (std::is_same<R, float>::value) {
+        // complex64: one table read, W^k; the factor of input j = j2 + N2 j1
+        // is W^{k j2} (W^{k N2})^{j1}, each formed by at most N2 - 1 + 3 + 3
+        // FP64 products from W^k
+        uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TW);
+        __asm__ __volatile__("" : "+v"(kb));
+        double wr, wi;
+        twiddle_base(tw, two, kb, wr, wi);
+        if (DIR > 0) wi = -wi;
+        double sr = wr, si = wi;  // W^{k N2}
+#pragma unroll
+        for (int q = 1; q < N2; q *= 2) cmul64(sr, si, sr, si);
+        double gr = 1.0, gi = 0.0;  // W^{k j2}
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) {
+            double cr = gr, ci = gi;
+#pragma unroll
+            for (int j1 = 0; j1 < N1; ++j1) {
+                const int j = N2 * j1 + j2;
+                a[j2][j1] = j == 0 ? v[0] : mul_round(v[j], cr, ci);
+                if (j1 + 1 < N1) cmul64(cr, ci, sr, si);
+            }
+            dft<N1, DIR>(a[j2]);
+            if (j2 + 1 < N2) cmul64(gr, gi, wr, wi);
+        }
+    } else {
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2) {
         // an opaque copy of the index pins this group's table loads here: the
@@ -263,6 +319,7 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
             a[j2][j1] = j == 0 ? v[0] : twiddle<DIR>(v[j], tw, two + (j - 1) * L, kb);
         }
         dft<N1, DIR>(a[j2]);
+    }
     }
     twiddle_grid<NR, DIR, N1, N2>(a);
 #pragma unroll
@@ -359,8 +416,21 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
                 // pins the table loads to this stage (see tw_dft)
                 uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TwEntry<R>);
                 __asm__ __volatile__("" : "+v"(kb));
+                if constexpr (std::is_same<R, float>::value) {
+                    // complex64: W^{jk} = (W^k)^j in FP64 from the one table value
+                    double wr, wi;
+                    twiddle_base(tw, TWO, kb, wr, wi);
+                    if (DIR > 0) wi = -wi;
+                    double cr = wr, ci = wi;
 #pragma unroll
-                for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L, kb);
+                    for (int j = 1; j < r; ++j) {
+                        u[j] = mul_round(u[j], cr, ci);
+                        if (j + 1 < r) cmul64(cr, ci, wr, wi);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 1; j < r; ++j) u[j] = twiddle<DIR>(u[j], tw, TWO + (j - 1) * L, kb);
+                }
             }
             dft<r, DIR>(u);
         }
