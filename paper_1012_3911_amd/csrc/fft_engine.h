@@ -275,19 +275,28 @@ template <int NR, int DIR, typename R> __device__ __forceinline__ void dft(cx<R>
 // just before it, so that at most four table entries are live at a time
 // instead of NR - 1 (for complex64 each entry is an FP32 hi/lo pair, four
 // registers).  Same arithmetic as twiddle() followed by dft<NR>().
-template <int NR, int DIR, typename R, typename TW>
-__device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int two, int L, int k)
+template <int NR, int DIR, bool PRE, typename R, typename TW>
+__device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int two, int L, int k, double pwr,
+                                       double pwi)
 {
     constexpr int N1 = 4, N2 = NR / 4;
     cx<R> a[N2][N1];
     if constexpr (std::is_same<R, float>::value) {
-        // complex64: one table read, W^k; the factor of input j = j2 + N2 j1
-        // is W^{k j2} (W^{k N2})^{j1}, each formed by at most N2 - 1 + 3 + 3
-        // FP64 products from W^k
-        uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TW);
-        __asm__ __volatile__("" : "+v"(kb));
-        double wr, wi;
-        twiddle_base(tw, two, kb, wr, wi);
+        // complex64: W^k (read here, or PRE: read at the start of the pass,
+        // pwr + i pwi); the factor of input j = j2 + N2 j1 is
+        // W^{k j2} (W^{k N2})^{j1}, each formed by at most N2 - 1 + 3 + 3 FP64
+        // products from W^k
+        double wr = pwr, wi = pwi;
+        if constexpr (!PRE) {
+            uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TW);
+            __asm__ __volatile__("" : "+v"(kb));
+            twiddle_base(tw, two, kb, wr, wi);
+        } else {
+            // opaque copies: the factors of two transforms of the same line
+            // (two states, or the forward and inverse transforms) are then
+            // formed afresh in each instead of being kept live between them
+            __asm__ __volatile__("" : "+v"(wr), "+v"(wi));
+        }
         if (DIR > 0) wi = -wi;
         double sr = wr, si = wi;  // W^{k N2}
 #pragma unroll
@@ -383,12 +392,32 @@ template <int N, int RAD> struct LineShape {
     static constexpr int TW_SIZE = tw_offset(NST);
 };
 
+// W^k in FP64 of the thread's butterfly in each twiddled stage (S >= 1, one
+// butterfly per thread there) of an N-point line, read once per pass so that
+// the complex64 transforms of the pass read no table (see tw_dft).
+template <int N, int RAD> struct TwBase {
+    static constexpr int NT = LineShape<N, RAD>::NST > 1 ? LineShape<N, RAD>::NST - 1 : 1;
+    double r[NT], i[NT];
+};
+template <int N, int RAD, int S = 1>
+__device__ __forceinline__ void tw_base_load(TwBase<N, RAD> &w, const TwEntry<float> *__restrict__ tw, int t)
+{
+    using Sh = LineShape<N, RAD>;
+    if constexpr (S < Sh::NST) {
+        static_assert(Sh::RV / Sh::radix(S) == 1, "one butterfly per thread in a twiddled stage");
+        constexpr int L = Sh::span(S);
+        twiddle_base(tw, Sh::tw_offset(S), (uint32_t)(t & (L - 1)) * (uint32_t)sizeof(TwEntry<float>), w.r[S - 1],
+                     w.i[S - 1]);
+        tw_base_load<N, RAD, S + 1>(w, tw, t);
+    }
+}
+
 // One Stockham stage S of an N-point transform (see the file comment).
 // v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in
 // line; tw: the stage twiddle table of this (N, RAD).
-template <typename R, int N, int RAD, int DIR, int S, class MAP, int NV>
+template <typename R, int N, int RAD, int DIR, int S, class MAP, bool PRE, int NV>
 __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                          bool act = true)
+                                          const TwBase<N, RAD> &wb, bool act = true)
 {
     using Sh = LineShape<N, RAD>;
     static_assert(NV == Sh::RV, "register array size must match the line shape");
@@ -410,7 +439,8 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         const int b = t + i * T;
         const int k = b & (L - 1);
         if constexpr (L > 1 && r >= 8 && SFO_TW_GROUPED) {
-            tw_dft<r, DIR>(u, tw, TWO, L, k);
+            constexpr int WB = S >= 1 ? S - 1 : 0;
+            tw_dft<r, DIR, PRE>(u, tw, TWO, L, k, PRE ? wb.r[WB] : 0.0, PRE ? wb.i[WB] : 0.0);
         } else {
             if constexpr (L > 1) {
                 // pins the table loads to this stage (see tw_dft)
@@ -419,7 +449,14 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
                 if constexpr (std::is_same<R, float>::value) {
                     // complex64: W^{jk} = (W^k)^j in FP64 from the one table value
                     double wr, wi;
-                    twiddle_base(tw, TWO, kb, wr, wi);
+                    if constexpr (PRE) {
+                        static_assert(NB == 1, "one butterfly per thread in a twiddled stage");
+                        wr = wb.r[S - 1];
+                        wi = wb.i[S - 1];
+                        __asm__ __volatile__("" : "+v"(wr), "+v"(wi));  // see tw_dft
+                    } else {
+                        twiddle_base(tw, TWO, kb, wr, wi);
+                    }
                     if (DIR > 0) wi = -wi;
                     double cr = wr, ci = wi;
 #pragma unroll
@@ -467,29 +504,44 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
 }
 
 // Full N-point transform of the thread's cyclic values (direction DIR), with
-// the LDS exchanges placed by MAP (RowMap<R, RAD> or ColMap<C>).
-template <typename R, int N, int RAD, int DIR, class MAP, int S, int NV>
-__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                         bool act, int)
+// the LDS exchanges placed by MAP (RowMap<R, RAD> or ColMap<C>).  PRE: the
+// complex64 stage factors come from wb (see TwBase) instead of the table.
+template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int S, int NV>
+__device__ __forceinline__ void fft_line_st(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                            const TwBase<N, RAD> &wb, bool act)
 {
-    if constexpr (S - 1 < LineShape<N, RAD>::NST) {
-        fft_stage<R, N, RAD, DIR, S - 1, MAP>(v, sh, t, tw, act);
-        fft_line<R, N, RAD, DIR, MAP, S + 1>(v, sh, t, tw, act, 0);
+    if constexpr (S < LineShape<N, RAD>::NST) {
+        fft_stage<R, N, RAD, DIR, S, MAP, PRE>(v, sh, t, tw, wb, act);
+        fft_line_st<R, N, RAD, DIR, MAP, PRE, S + 1>(v, sh, t, tw, wb, act);
     }
 }
 
-template <typename R, int N, int RAD, int DIR, class MAP, int S = 0, int NV>
+template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int NV>
+__device__ __forceinline__ void fft_line_impl(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                              const TwBase<N, RAD> &wb, bool act)
+{
+    // a fresh copy of the thread index per transform: the exchange
+    // addresses of two transforms in a row are then not shared (and kept
+    // live) between them
+    int tt = t;
+    __asm__ __volatile__("" : "+v"(tt));
+    fft_line_st<R, N, RAD, DIR, MAP, PRE, 0>(v, sh, tt, tw, wb, act);
+}
+
+template <typename R, int N, int RAD, int DIR, class MAP, int NV>
 __device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
                                          bool act = true)
 {
-    if constexpr (S == 0) {
-        // a fresh copy of the thread index per transform: the exchange
-        // addresses of two transforms in a row are then not shared (and kept
-        // live) between them
-        int tt = t;
-        __asm__ __volatile__("" : "+v"(tt));
-        fft_line<R, N, RAD, DIR, MAP, 1>(v, sh, tt, tw, act, 0);
-    }
+    TwBase<N, RAD> unused;
+    fft_line_impl<R, N, RAD, DIR, MAP, false>(v, sh, t, tw, unused, act);
+}
+
+// The same with the stage factors of a complex64 line taken from wb.
+template <typename R, int N, int RAD, int DIR, class MAP, int NV>
+__device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                         const TwBase<N, RAD> &wb, bool act = true)
+{
+    fft_line_impl<R, N, RAD, DIR, MAP, std::is_same<R, float>::value>(v, sh, t, tw, wb, act);
 }
 
 // ---------------------------------------------------------------- phases --

@@ -189,8 +189,9 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
 template <typename R, int N, int RAD, int NS, bool PAD, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
                                          VStore<R> (&vv)[NV], int64_t row0, int line, int ny, cx<R> *sh, int t,
-                                         const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
-                                         int mode, double (&mom)[3], const VStore<R> *__restrict__ V0late = nullptr)
+                                         const TwEntry<R> *__restrict__ tw, const TwBase<N, RAD> &wb, const PhaseArgs &ph,
+                                         const GradArgs &ga, int mode, double (&mom)[3],
+                                         const VStore<R> *__restrict__ V0late = nullptr)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     // everything below is derived from an opaque copy of t: in a persistent
@@ -202,7 +203,12 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     using Map = RowMap<R, RAD, PAD>;
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < NS; ++q) {
+            if constexpr (RAD == 16)
+                fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
+            else
+                fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        }
     // potential loaded here rather than before the transform: fewer registers held through it
     const int64_t row = row0 + line;
     const uint32_t lt = (uint32_t)(line * N + t);
@@ -298,7 +304,12 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     }
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < NS; ++q) {
+            if constexpr (RAD == 16)
+                fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
+            else
+                fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+        }
 }
 
 template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16), bool LATE = false>
@@ -313,11 +324,15 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     cx<R> v[NS][RV];
     VStore<R> vv[RV];
     uint32_t lt = (uint32_t)(line * N + t);
+    // complex64 radix-16 rows read their stage twiddles here, with the line
+    // (measured: faster for these; radix-8 rows and columns read them per stage)
+    TwBase<N, RAD> wb;
+    if constexpr (std::is_same<R, float>::value && RAD == 16) tw_base_load(wb, tw, t);
     row_load<R, N, RAD, NS>(v, S, row0, lt);
     // the potential loads complete under the inverse transform (or, LATE, are issued after it)
     if (!LATE && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0, row0, lt);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS, PAD>(v, vv, row0, line, ny, sh, t, tw, ph, ga, mode, mom, LATE ? V0 : nullptr);
+    row_body<R, N, RAD, NS, PAD>(v, vv, row0, line, ny, sh, t, tw, wb, ph, ga, mode, mom, LATE ? V0 : nullptr);
     // the offset is recomputed rather than held through the transforms
     __asm__ __volatile__("" : "+v"(lt));
     row_store<R, N, RAD, NS>(v, S, row0, lt);
