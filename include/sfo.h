@@ -71,7 +71,8 @@ enum {
 
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3 (Dirac: 2) */
-    int64_t n[3];      /* points per axis, x first; powers of two, 1-D 64..8192, 2-D/3-D 64..4096 */
+    int64_t n[3];      /* points per axis, x first; powers of two, 1-D 64..8192, 2-D/3-D 64..4096,
+                          at most 2^35 bytes (32 GiB) per state component */
     double xmin[3];    /* box per axis, x first */
     double xmax[3];
     int32_t equation;  /* SFO_SCHRODINGER or SFO_DIRAC */

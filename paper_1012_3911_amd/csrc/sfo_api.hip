@@ -1062,6 +1062,13 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
                         (long long)maxn);
         ntot *= d.n[a];
     }
+    // the line passes address a work-group's lines by 32-bit byte offsets from
+    // a scalar base: at most (N / 8) lines of stride <= plane / N apart, below
+    // 2^32 for a state plane of at most 2^35 bytes
+    const int64_t plane_bytes = ntot * (d.dtype == SFO_C128 ? 16 : 8);
+    if (plane_bytes > ((int64_t)1 << 35))
+        return fail(SFO_E_UNSUPPORTED, "a state of %lld bytes per component exceeds the 32 GiB the passes address",
+                    (long long)plane_bytes);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     int ndev = 0;

@@ -62,6 +62,8 @@ def _desc(**kw):
     (dict(xmax=-2.0), -1), (dict(dt=0.0), -1), (dict(dt=float("nan")), -1), (dict(dtype=7), -1),
     (dict(equation=3), -1), (dict(equation=1, ndim=3, n=(64, 64, 64)), -1),
     (dict(n=(32, 64, 1)), -2), (dict(n=(8192, 64, 1)), -2), (dict(ndim=1, n=(16384, 1, 1)), -2),
+    # beyond the 32-bit offsets of the passes: 2^36 bytes of complex64, 2^36 of complex128
+    (dict(ndim=3, n=(4096, 4096, 512), dtype=0), -2), (dict(ndim=3, n=(4096, 4096, 256), dtype=1), -2),
 ])
 def test_invalid_descriptors(lib, kw, status):
     d = _desc(**kw)
