@@ -17,9 +17,12 @@ reverse sweep (adjoint) of the same workload and the 64-problem batched
 control workload (forward, and forward + reverse sweep).
 
 Roofline: the dominant pass's algorithmic bytes per launch divided by its
-average launch duration, timed with HIP events around back-to-back launches
-on the grid's stream; `traffic` is the HBM bytes per launch measured with
-rocprofv3 counters for the same kernel sources (null otherwise).
+average launch duration within steps of the propagation's pass sequence,
+each launch timestamped by its own dispatch (start/stop events of the
+launch, on the grid's stream); back-to-back launches of one pass, which read
+their own output partly from cache, are reported beside it.  `traffic` is
+the HBM bytes per launch measured with rocprofv3 counters for the same
+kernel sources (null otherwise).
 
 Prints ONE JSON line.  --gpus N with N > 1 is refused: the library runs on
 one GPU.
@@ -120,11 +123,14 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g.propagate(psi, 0, wl.nsteps)
     drift = g.norm(psi) / n0 - 1
     final = psi.cpu().numpy()
-    # per-kernel durations: back-to-back launches of each pass between two HIP
-    # events on the grid's stream, and the timed sequence again with an event
-    # pair around every launch (which adds the dispatch gap to each)
-    kern = {name: g.time_pass(kind, 200) for name, kind in
-            (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
+    # per-kernel durations: within steps of the pass sequence, each launch
+    # timestamped by its own dispatch (the figure the roofline uses); back to
+    # back launches of one pass (which finds its own output partly in cache);
+    # and the timed sequence again with an event pair around every launch
+    # (which adds the dispatch gap to each)
+    kinds = (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))
+    kern = {name: g.time_pass(kind, 200, in_step=True) for name, kind in kinds}
+    kern_b2b = {name: g.time_pass(kind, 200) for name, kind in kinds}
     g.profile(True)
     run_steps(g, psi, min(steps, 2 * wl.nsteps), wl.nsteps)
     kern_ev = {name: g.profile_read(kind) for name, kind in
@@ -147,8 +153,8 @@ def bench_path(wl, dtype, flags, steps, warmup):
     g.close()
     del psi
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, kernels_ev=kern_ev, plan=plan,
-                fwd_adj_seconds=fa)
+    return dict(seconds=t1 - t0, drift=drift, final=final, kernels=kern, kernels_b2b=kern_b2b, kernels_ev=kern_ev,
+                plan=plan, fwd_adj_seconds=fa)
 
 
 def bench_batch(reps=3):
@@ -211,7 +217,8 @@ def bench_beyond_mall(steps=40):
     g.propagate(psi, 0, steps)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    kern = {name: g.time_pass(kind, 50) for name, kind in (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
+    kern = {name: g.time_pass(kind, 50, in_step=True)
+            for name, kind in (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
     g.close()
     del psi
     torch.cuda.empty_cache()
@@ -305,6 +312,8 @@ def main():
     for k, avg in r["kernels"].items():
         cnt, tot = r["kernels_ev"][k]
         kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches_per_step=1,
+                         timing="in-step, per-dispatch timestamps",
+                         avg_us_back_to_back=1e3 * r["kernels_b2b"][k],
                          avg_us_event_per_launch=1e3 * tot / cnt if cnt else None)
     dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
     achieved = kstats[dom]["gbs"]

@@ -185,8 +185,11 @@ sfo_status sfo_batch_check(sfo_batch b);
 
 /* Tile-shape planning.  Each line pass exists in several shapes (lines per
  * work-group, register radix, occupancy hint).  sfo_autotune times every
- * shape of every pass of this grid `reps` times on a scratch state the call
- * allocates and frees, keeps the fastest, and remembers the choice for later
+ * shape of every pass of this grid on a scratch state the call allocates and
+ * frees (2-D and 3-D Schroedinger: `reps` whole steps of the propagation's
+ * pass sequence, x shapes first with the current others, then each further
+ * axis; the reverse sweep's two-state passes likewise; otherwise `reps`
+ * launches of each pass), keeps the fastest, and remembers the choice for later
  * grids of the same shape, precision and equation in this process and, if
  * the environment variable SFO_TUNE_CACHE names a file, in that file.
  * Synchronises the stream.  sfo_get_plan / sfo_set_plan read and force the
@@ -214,10 +217,17 @@ sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *to
 /* Average duration in milliseconds of one launch of the grid's current
  * shape of a pass (SFO_KERNEL_ROW: inverse x-transform, potential factor,
  * forward x-transform; SFO_KERNEL_COLUMN / ZCOLUMN: transform, kinetic
- * factor, inverse transform), from `reps` back-to-back launches on a scratch
- * state (allocated and freed by the call) between two HIP events on the
- * grid's stream.  Unlike sfo_profile_read, no event sits between launches.
- * 2-D and 3-D Schroedinger grids; synchronises the stream. */
+ * factor, inverse transform), on a scratch state (allocated and freed by the
+ * call).  By default from `reps` back-to-back launches of that pass between
+ * two HIP events on the grid's stream: each launch then reads what the
+ * previous launch of the same pass wrote, partly from cache.  With
+ * SFO_TIME_IN_STEP or'ed into kind: `reps` (at most 4096) steps of the pass
+ * sequence a propagation runs (row pass, then the other axes), each launch
+ * of the pass timestamped by its own dispatch (hipExtLaunchKernelGGL start
+ * and stop events); for SFO_KERNEL_COLUMN in 3-D, the y-forward pass.
+ * Unlike sfo_profile_read, no event packet sits between launches.  2-D and
+ * 3-D Schroedinger grids; synchronises the stream. */
+enum { SFO_TIME_IN_STEP = 16 };
 sfo_status sfo_time_pass(sfo_grid g, int32_t kind, int32_t reps, double *avg_ms);
 
 /* Description of the last failure on the calling thread ("" if none). */

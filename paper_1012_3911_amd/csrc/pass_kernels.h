@@ -6,6 +6,8 @@
 #pragma once
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "sfo_impl.h"
 
 namespace sfo {
@@ -618,6 +620,17 @@ __device__ __forceinline__ void adj1d_tile(cx<R> *__restrict__ psi, cx<R> *__res
 }
 
 // ------------------------------------------------------ variant dispatch --
+// A kernel launch; ev != null: an event pair that the dispatch itself
+// timestamps at its start and end (no packet between launches).
+template <typename K, typename... A>
+void launch_kernel(K kernel, dim3 grid, dim3 block, hipStream_t st, const hipEvent_t *ev, A... args)
+{
+    if (ev)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev[0], ev[1], 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 template <typename R, int N, int V> constexpr bool row_variant_ok()
 {
     constexpr RowVariant rv = kRowVariants[V];
@@ -630,7 +643,7 @@ template <typename R, int N, int V> constexpr bool row_variant_ok()
 template <typename R, int N, int V, int NS>
 hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0, const void *const *tws,
                       const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st, const GroupArgs<R> &grp,
-                      int ngroup)
+                      int ngroup, const hipEvent_t *ev)
 {
     if constexpr (!row_variant_ok<R, N, V>()) {
         return hipErrorInvalidValue;
@@ -640,13 +653,13 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
         using Tl = RowTile<N, rv.rad, rv.threads>;
         if (nrows % Tl::ROWS) {
             // fewer rows than a work-group holds (a single 1-D line): one row per group
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS, rv.pad>),
-                               dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), 0, st, S, ny,
-                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
+            launch_kernel(k_xpass<R, N, rv.rad, LineShape<N, rv.rad>::T, 1, NS, rv.pad>,
+                          dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), st, ev, S, ny,
+                          (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         } else {
-            hipLaunchKernelGGL((k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late>),
-                               dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), 0, st, S, ny,
-                               (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
+            launch_kernel(k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late>,
+                          dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), st, ev, S, ny,
+                          (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         }
         return hipGetLastError();
     }
@@ -655,10 +668,10 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
 template <typename R, int N, int NS, size_t... I>
 hipError_t row_dispatch(int var, const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0,
                         const void *const *tw, const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st,
-                        const GroupArgs<R> &grp, int ngroup, std::index_sequence<I...>)
+                        const GroupArgs<R> &grp, int ngroup, const hipEvent_t *ev, std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
-    ((var == (int)I ? (r = row_launch<R, N, (int)I, NS>(S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup), 0)
+    ((var == (int)I ? (r = row_launch<R, N, (int)I, NS>(S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup, ev), 0)
                     : 0),
      ...);
     return r;
@@ -674,7 +687,7 @@ template <typename R, int N, int V> constexpr bool col_variant_ok()
 template <typename R, int N, int V, int NS>
 hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
                       const void *const *tws, const KinArgs &kin, int mode, hipStream_t st, const GroupArgs<R> &grp,
-                      int ngroup)
+                      int ngroup, const hipEvent_t *ev)
 {
     if constexpr (!col_variant_ok<R, N, V>()) {
         return hipErrorInvalidValue;
@@ -685,10 +698,10 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
         // per-thread byte offsets within a work-group's lines are 32-bit
         if (((int64_t)(LineShape<N, cv.rad>::T - 1) * stride + cv.cols) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>),
-                           dim3((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup),
-                           dim3(cv.cols * LineShape<N, cv.rad>::T), 0, st, S, stride, slab_stride,
-                           (const TwEntry<R> *)tw, kin, mode, grp);
+        launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>,
+                      dim3((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup),
+                      dim3(cv.cols * LineShape<N, cv.rad>::T), st, ev, S, stride, slab_stride,
+                      (const TwEntry<R> *)tw, kin, mode, grp);
         return hipGetLastError();
     }
 }
@@ -696,11 +709,11 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
 template <typename R, int N, int NS, size_t... I>
 hipError_t col_dispatch(int var, const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab,
                         int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st,
-                        const GroupArgs<R> &grp, int ngroup, std::index_sequence<I...>)
+                        const GroupArgs<R> &grp, int ngroup, const hipEvent_t *ev, std::index_sequence<I...>)
 {
     hipError_t r = hipErrorInvalidValue;
     ((var == (int)I
-          ? (r = col_launch<R, N, (int)I, NS>(S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup),
+          ? (r = col_launch<R, N, (int)I, NS>(S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup, ev),
              0)
           : 0),
      ...);

@@ -517,6 +517,49 @@ double time_col2(sfo_grid g, int ax, int v, cx<R> *psi, cx<R> *adj, hipEvent_t e
     });
 }
 
+// One step of the pass sequence a propagation runs, with the given shapes,
+// on scratch buffers: the row pass, then (2-D) the column pass with the
+// kinetic factor, or (3-D) y-forward, z with the kinetic factor, y-inverse.
+// ns = 2: the reverse sweep's two-state passes (adjoint, dL/dV0 accumulator
+// and partial slots).  The launch of kind `ek` (the first y-pass for
+// SFO_KERNEL_COLUMN in 3-D) is timestamped by its own dispatch with ev.
+template <typename R>
+hipError_t step_sequence(sfo_grid g, int rv, const int *cv, int ns, cx<R> *psi, cx<R> *adj, double *acc,
+                         double *part, int ek = -1, const hipEvent_t *ev = nullptr)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const StatePtrs<R> S{{psi, ns == 2 ? adj : nullptr}};
+    const int sgn = ns == 2 ? -1 : +1;
+    const PhaseArgs ph = phase_args(g, -1, 0, sgn);
+    GradArgs ga{};
+    if (ns == 2) {
+        ga.acc = acc;
+        ga.wacc = 1.0;
+        ga.part = part;
+    }
+    auto evk = [&](int k) { return k == ek ? ev : nullptr; };
+    const int rmode = M_INV | M_PHASE | M_FWD | (ns == 2 ? M_GRAD : 0);
+    hipError_t e = launch_xpass<R>(rv, (int)nx, ns, S, ny * nz, (int)ny, g->V0, (const void *const *)g->tw[0], ph, ga,
+                                   rmode, g->st, GroupArgs<R>{}, 1, evk(SFO_KERNEL_ROW));
+    if (e != hipSuccess) return e;
+    const void *const *tw1 = (const void *const *)g->tw[1];
+    const int cmode = M_FWD | M_KIN | M_INV;
+    if (g->ndim == 2) {
+        const KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
+        return launch_colpass<R>(cv[1], (int)ny, ns, S, nx, nx, 1, 0, tw1, k, cmode, g->st, GroupArgs<R>{}, 1,
+                                 evk(SFO_KERNEL_COLUMN));
+    }
+    const KinArgs none{g->one, g->one, g->one, 1, 1};
+    const KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
+    e = launch_colpass<R>(cv[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD, g->st, GroupArgs<R>{}, 1,
+                          evk(SFO_KERNEL_COLUMN));
+    if (e != hipSuccess) return e;
+    e = launch_colpass<R>(cv[2], (int)nz, ns, S, nx * ny, nx * ny, 1, 0, (const void *const *)g->tw[2], k, cmode,
+                          g->st, GroupArgs<R>{}, 1, evk(SFO_KERNEL_ZCOLUMN));
+    if (e != hipSuccess) return e;
+    return launch_colpass<R>(cv[1], (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_INV, g->st);
+}
+
 // Scratch state and an event pair for the timing helpers.
 struct TimingScratch {
     void *mem = nullptr;
@@ -556,6 +599,60 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         return m;
     };
     double best = 1e30;
+    const bool seq = g->d.equation == SFO_SCHRODINGER && g->ndim >= 2;
+    if (seq) {
+        // whole steps of the propagation's pass sequence: a pass reads what
+        // the other passes wrote (a back-to-back launch of one pass would
+        // find its own output in the caches); rows given the current column
+        // shapes, then each column axis given the rest
+        auto tune = [&](int ns, int &rv, int *cv, cx<R> *adj, double *acc, double *part) {
+            auto steps = [&](int r, const int *c) {
+                return time_launches(g, ts.a, ts.b, reps,
+                                     [&] { return step_sequence<R>(g, r, c, ns, psi, adj, acc, part); });
+            };
+            double b = 1e30;
+            for (int v = 0; v < kNumRowVariants; ++v) {
+                if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
+                const double ms = best_of([&] { return steps(v, cv); });
+                if (ms >= 0 && ms < b) { b = ms; rv = v; }
+            }
+            for (int ax = 1; ax < g->ndim; ++ax) {
+                const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
+                b = 1e30;
+                int keep = cv[ax];
+                for (int v = 0; v < kNumColVariants; ++v) {
+                    if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+                    cv[ax] = v;
+                    const double ms = best_of([&] { return steps(rv, cv); });
+                    if (ms >= 0 && ms < b) { b = ms; keep = v; }
+                }
+                cv[ax] = keep;
+            }
+        };
+        int cv[3] = {0, g->col_var[1], g->col_var[2]};
+        tune(1, g->row_var, cv, nullptr, nullptr, nullptr);
+        g->col_var[1] = cv[1];
+        g->col_var[2] = cv[2];
+        // the reverse sweep's two-state passes, on a second state, an accumulator and partial slots
+        const int64_t nrows = g->n[1] * g->n[2];
+        const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
+        const size_t ebytes = sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows);
+        void *extra = nullptr;
+        HIP_TRY(hipMalloc(&extra, ebytes));
+        hipError_t he = hipMemsetAsync(extra, 0, ebytes, g->st);
+        if (he == hipSuccess) {
+            double *acc = (double *)((char *)extra + sbytes);
+            int rv2 = g->row_var, cv2[3] = {0, g->col_var[1], g->col_var[2]};
+            tune(2, rv2, cv2, (cx<R> *)extra, acc, acc + g->ntot);
+            g->row_var2 = rv2;
+            g->col_var2[1] = cv2[1];
+            g->col_var2[2] = cv2[2];
+            he = hipStreamSynchronize(g->st);
+        }
+        (void)hipFree(extra);
+        if (he != hipSuccess) return fail(SFO_E_HIP, "autotune (reverse sweep): %s", hipGetErrorString(he));
+        return SFO_OK;
+    }
     for (int v = 0; v < kNumRowVariants; ++v) {
         if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
         const double ms = best_of([&] { return time_row<R>(g, v, psi, ts.a, ts.b, reps); });
@@ -609,6 +706,31 @@ template <typename R> sfo_status time_pass_impl(sfo_grid g, int kind, int reps, 
     sfo_status s = timing_setup<R>(g, ts);
     if (s) return s;
     cx<R> *psi = (cx<R> *)ts.mem;
+    if (kind & SFO_TIME_IN_STEP) {
+        // steps of the propagation's pass sequence; each launch of the pass is
+        // timestamped by its own dispatch (one event pair per step)
+        kind &= ~SFO_TIME_IN_STEP;
+        const int cv[3] = {0, g->col_var[1], g->col_var[2]};
+        std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = step_sequence<R>(g, g->row_var, cv, 1, psi, nullptr, nullptr, nullptr);
+        for (int i = 0; i < reps && e == hipSuccess; ++i)
+            e = step_sequence<R>(g, g->row_var, cv, 1, psi, nullptr, nullptr, nullptr, kind, &ev[2 * (size_t)i]);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+        double total = 0.0;
+        for (int i = 0; i < reps && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[2 * (size_t)i], ev[2 * (size_t)i + 1]);
+            total += ms;
+        }
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (e != hipSuccess) return fail(SFO_E_HIP, "in-step timing failed: %s", hipGetErrorString(e));
+        *avg_ms = total / reps;
+        return SFO_OK;
+    }
     double ms = -1.0;
     if (kind == SFO_KERNEL_ROW) ms = time_row<R>(g, g->row_var, psi, ts.a, ts.b, reps);
     else if (kind == SFO_KERNEL_COLUMN) ms = time_col<R>(g, 1, g->col_var[1], psi, ts.a, ts.b, reps);
@@ -1268,8 +1390,10 @@ sfo_status sfo_time_pass(sfo_grid g, int32_t kind, int32_t reps, double *avg_ms)
     if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
         return fail(SFO_E_UNSUPPORTED, "pass timing is for 2-D and 3-D Schroedinger grids");
     if (reps < 1) return fail(SFO_E_INVALID, "reps must be positive");
-    if (kind != SFO_KERNEL_ROW && kind != SFO_KERNEL_COLUMN && !(kind == SFO_KERNEL_ZCOLUMN && g->ndim == 3))
+    const int k = kind & ~SFO_TIME_IN_STEP;
+    if (k != SFO_KERNEL_ROW && k != SFO_KERNEL_COLUMN && !(k == SFO_KERNEL_ZCOLUMN && g->ndim == 3))
         return fail(SFO_E_INVALID, "no pass of kind %d on this grid", kind);
+    if ((kind & SFO_TIME_IN_STEP) && reps > 4096) return fail(SFO_E_INVALID, "in-step timing takes at most 4096 reps");
     return g->c128 ? time_pass_impl<double>(g, kind, reps, avg_ms) : time_pass_impl<float>(g, kind, reps, avg_ms);
 }
 

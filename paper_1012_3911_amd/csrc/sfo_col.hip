@@ -6,17 +6,17 @@ namespace sfo {
 template <typename R>
 hipError_t launch_colpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab,
                           int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode, hipStream_t st,
-                          const GroupArgs<R> &grp, int ngroup)
+                          const GroupArgs<R> &grp, int ngroup, const hipEvent_t *ev)
 {
     if (ns == 2) {
 #define CALL(n)                                                                                       \
-    col_dispatch<R, n, 2>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup, \
+    col_dispatch<R, n, 2>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup, ev, \
                           std::make_index_sequence<kNumColVariants>{})
         SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
     }
 #define CALL(n)                                                                                       \
-    col_dispatch<R, n, 1>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup, \
+    col_dispatch<R, n, 1>(variant, S, ncols, stride, nslab, slab_stride, tw, kin, mode, st, grp, ngroup, ev, \
                           std::make_index_sequence<kNumColVariants>{})
     SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
@@ -46,9 +46,9 @@ template bool colpass_variant_ok<double>(int, int, int64_t);
 
 template hipError_t launch_colpass<float>(int, int, int, const StatePtrs<float> &, int64_t, int64_t, int, int64_t,
                                           const void *const *, const KinArgs &, int, hipStream_t,
-                                          const GroupArgs<float> &, int);
+                                          const GroupArgs<float> &, int, const hipEvent_t *);
 template hipError_t launch_colpass<double>(int, int, int, const StatePtrs<double> &, int64_t, int64_t, int, int64_t,
                                            const void *const *, const KinArgs &, int, hipStream_t,
-                                           const GroupArgs<double> &, int);
+                                           const GroupArgs<double> &, int, const hipEvent_t *);
 
 }  // namespace sfo

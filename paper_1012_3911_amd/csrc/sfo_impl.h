@@ -141,15 +141,18 @@ constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 // tw[0], tw[1]: the stage twiddle tables of the line length for radix 8 and 16.
 // grp / ngroup: a grouped launch over ngroup problems of the same shape
 // (S, V0, the phase and gradient arguments then come from the descriptors).
+// ev: null, or an event pair the dispatch timestamps at its start and end.
 template <typename R>
 hipError_t launch_xpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t nrows, int ny,
                         const void *V0, const void *const *tw, const PhaseArgs &ph, const GradArgs &ga,
-                        int mode, hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
+                        int mode, hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1,
+                        const hipEvent_t *ev = nullptr);
 
 template <typename R>
 hipError_t launch_colpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t ncols, int64_t stride,
                           int nslab, int64_t slab_stride, const void *const *tw, const KinArgs &kin, int mode,
-                          hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1);
+                          hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{}, int ngroup = 1,
+                          const hipEvent_t *ev = nullptr);
 
 template <typename R>
 hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a,

@@ -8,17 +8,17 @@ namespace sfo {
 template <typename R>
 hipError_t launch_xpass(int variant, int N, int ns, const StatePtrs<R> &S, int64_t nrows, int ny, const void *V0,
                         const void *const *tw, const PhaseArgs &ph, const GradArgs &ga, int mode, hipStream_t st,
-                        const GroupArgs<R> &grp, int ngroup)
+                        const GroupArgs<R> &grp, int ngroup, const hipEvent_t *ev)
 {
     if (ns == 2) {
 #define CALL(n)                                                                             \
-    row_dispatch<R, n, 2>(variant, S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup,   \
+    row_dispatch<R, n, 2>(variant, S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup, ev, \
                           std::make_index_sequence<kNumRowVariants>{})
         SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
     }
 #define CALL(n)                                                                             \
-    row_dispatch<R, n, 1>(variant, S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup,   \
+    row_dispatch<R, n, 1>(variant, S, nrows, ny, V0, tw, ph, ga, mode, st, grp, ngroup, ev, \
                           std::make_index_sequence<kNumRowVariants>{})
     SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
@@ -75,9 +75,9 @@ template bool xpass_variant_ok<double>(int, int);
 
 template hipError_t launch_xpass<float>(int, int, int, const StatePtrs<float> &, int64_t, int, const void *,
                                         const void *const *, const PhaseArgs &, const GradArgs &, int, hipStream_t,
-                                        const GroupArgs<float> &, int);
+                                        const GroupArgs<float> &, int, const hipEvent_t *);
 template hipError_t launch_xpass<double>(int, int, int, const StatePtrs<double> &, int64_t, int, const void *,
                                          const void *const *, const PhaseArgs &, const GradArgs &, int, hipStream_t,
-                                         const GroupArgs<double> &, int);
+                                         const GroupArgs<double> &, int, const hipEvent_t *);
 
 }  // namespace sfo

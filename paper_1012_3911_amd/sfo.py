@@ -58,6 +58,7 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
+TIME_IN_STEP = 16  # or'ed into a kernel kind: time the pass within whole steps
 
 
 def load_library(path: str = LIB_PATH):
@@ -252,10 +253,13 @@ class Grid:
                "sfo_profile_read")
         return cnt.value, ms.value
 
-    def time_pass(self, kind: int, reps: int = 100) -> float:
-        """Average milliseconds per launch of one pass shape, from back-to-back launches."""
+    def time_pass(self, kind: int, reps: int = 100, in_step: bool = False) -> float:
+        """Average milliseconds per launch of one pass shape: from back-to-back
+        launches of that pass, or (in_step) within steps of the propagation's
+        pass sequence, each launch timestamped by its own dispatch."""
         ms = ctypes.c_double()
-        _check(_lib.sfo_time_pass(self._h, int(kind), int(reps), ctypes.byref(ms)), "sfo_time_pass")
+        k = int(kind) | (TIME_IN_STEP if in_step else 0)
+        _check(_lib.sfo_time_pass(self._h, k, int(reps), ctypes.byref(ms)), "sfo_time_pass")
         return ms.value
 
     def fft(self, psi, sign: int = -1):

@@ -262,3 +262,38 @@ def test_time_pass_reports_the_current_shapes():
     with pytest.raises(sfo.SfoError):
         g1.time_pass(sfo.KERNEL_ROW, 5)
     g1.close()
+
+
+@pytest.mark.parametrize("n", [(256, 128), (64, 64, 128)])
+def test_time_pass_in_step(n):
+    """sfo_time_pass with SFO_TIME_IN_STEP: per-dispatch durations of each pass
+    within steps of the pass sequence (2-D and 3-D), positive, and together
+    no longer than a whole step of the same sequence (which also holds the
+    gaps between launches)."""
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    lo, hi = (-10.0,) * len(n), (10.0,) * len(n)
+    shape = n[::-1]
+    wl = W.Workload("t", "schrodinger", n, lo, hi, 0.02, 1, np.zeros(shape), np.ones(shape, complex))
+    g = make_grid(wl, "c64")
+    kinds = [sfo.KERNEL_ROW, sfo.KERNEL_COLUMN] + ([sfo.KERNEL_ZCOLUMN] if len(n) == 3 else [])
+    per = {k: g.time_pass(k, 20, in_step=True) for k in kinds}
+    assert all(0.0 < v < 100.0 for v in per.values()), per
+    psi = torch.ones(shape, dtype=torch.complex64, device="cuda")
+    g.propagate(psi, 0, 1)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(20):
+        g.propagate(psi, 0, 1)
+    t1.record()
+    torch.cuda.synchronize()
+    step_ms = t0.elapsed_time(t1) / 20
+    # a 3-D step runs the y-pass twice; the timed y-pass is the forward one
+    passes = sum(per.values()) + (per[sfo.KERNEL_COLUMN] if len(n) == 3 else 0.0)
+    assert passes < 1.5 * step_ms + 0.05, (per, step_ms)
+    with pytest.raises(sfo.SfoError):
+        g.time_pass(sfo.KERNEL_ROW, 5000, in_step=True)
+    g.close()
