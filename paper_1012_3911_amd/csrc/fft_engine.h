@@ -361,6 +361,7 @@ __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n
 // conflicts are lower for that shape.  The shifts were chosen with a 64-bank, 4-byte-word model of
 // the LDS over the write and read patterns of every stage for N = 256..4096.
 template <typename R, int RAD, bool PAD = (RAD == 16)> struct RowMap {
+    static constexpr bool TW_AT_ONCE_FP64 = false;
     static constexpr bool AFFINE = PAD;
     static constexpr int SH = AFFINE ? (sizeof(R) == 4 ? 5 : 4) : 3;
     static constexpr int MASK = sizeof(R) == 4 ? 31 : 15;
@@ -370,6 +371,10 @@ template <typename R, int RAD, bool PAD = (RAD == 16)> struct RowMap {
 };
 template <int C> struct ColMap {
     static constexpr bool AFFINE = true;
+    // complex128 column transforms read all of a stage's twiddles at its start
+    // (measured faster: one table latency per stage; their few waves per SIMD
+    // leave the registers for it)
+    static constexpr bool TW_AT_ONCE_FP64 = true;
     __device__ static int at(int p) { return (p + (p >> 3)) * C; }
     __host__ __device__ static constexpr int off(int d) { return (d + (d >> 3)) * C; }
     static constexpr int slots(int N) { return (N + N / 8) * C; }
@@ -438,7 +443,8 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         for (int j = 0; j < r; ++j) u[j] = v[i + j * NB];
         const int b = t + i * T;
         const int k = b & (L - 1);
-        if constexpr (L > 1 && r >= 8 && SFO_TW_GROUPED) {
+        if constexpr (L > 1 && r >= 8 && SFO_TW_GROUPED &&
+                      !(MAP::TW_AT_ONCE_FP64 && std::is_same<R, double>::value)) {
             constexpr int WB = S >= 1 ? S - 1 : 0;
             tw_dft<r, DIR, PRE>(u, tw, TWO, L, k, PRE ? wb.r[WB] : 0.0, PRE ? wb.i[WB] : 0.0);
         } else {

@@ -428,7 +428,10 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
             const double kr = kcr * l.re - kci * l.im, ki = kcr * l.im + kci * l.re;
 #pragma unroll
             for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)sgn * ki);
-            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four points at a time
+            // complex64: four points at a time; complex128 issues every table
+            // load at once (measured faster; its register budget allows it)
+            constexpr int KG = sizeof(R) == 8 ? 16 : 4;
+            if ((m & (KG - 1)) == KG - 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
     if (mode & M_INV)
