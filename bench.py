@@ -50,13 +50,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "454ed965d3b84fc61bec572a6e75fb4f7ef46ec089b679420d26c9e51393fd72",
+    "sources_sha256": "cd15b9df221c5d3661296f4b7c03aae5cf16d71e75be5d029d92d7de81e08d55",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
-    "row/0": (24856, 32768), "row/1": (24846, 32768), "row/2": (24971, 32768), "row/3": (24858, 32768),
-    "row/4": (38440, 65911), "row/5": (24800, 32768), "row/6": (24805, 32768), "row/7": (24801, 32768),
-    "column/0": (16797, 33003), "column/1": (16790, 32777), "column/2": (16790, 35454),
-    "column/4": (16790, 32833), "column/5": (16788, 33046), "column/7": (16968, 33747),
-    "column/8": (16786, 34473),
+    "row/0": (24724, 32768), "row/1": (24726, 32768), "row/2": (24719, 32768), "row/3": (24726, 32768),
+    "row/4": (24722, 32768), "row/5": (24702, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
+    "row/8": (24686, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
+    "row/12": (24721, 32768), "row/13": (24702, 32768),
+    "column/0": (16662, 32832), "column/1": (16658, 32790), "column/2": (16660, 33327),
+    "column/4": (16658, 32784), "column/5": (16653, 33204), "column/7": (16767, 32813),
+    "column/8": (16636, 35790),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
 

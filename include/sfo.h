@@ -224,7 +224,9 @@ sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *to
  * SFO_TIME_IN_STEP or'ed into kind: `reps` (at most 4096) steps of the pass
  * sequence a propagation runs (row pass, then the other axes), each launch
  * of the pass timestamped by its own dispatch (hipExtLaunchKernelGGL start
- * and stop events); for SFO_KERNEL_COLUMN in 3-D, the y-forward pass.
+ * and stop events; a timestamped dispatch ends with a wider release, which
+ * adds about a microsecond to its own duration); for SFO_KERNEL_COLUMN in
+ * 3-D, the y-forward pass.
  * Unlike sfo_profile_read, no event packet sits between launches.  2-D and
  * 3-D Schroedinger grids; synchronises the stream. */
 enum { SFO_TIME_IN_STEP = 16 };
