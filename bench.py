@@ -201,6 +201,66 @@ def bench_batch(reps=3):
             "fwd_adjoint_updates_per_s": pts * S * reps / (t2 - t1)}
 
 
+def bench_config(wl, dtype, runs=2):
+    """Whole runs of one of the other workloads (1-D harmonic oscillator, 3-D
+    wells, 2-D Dirac): ms per step, updates/s, and for the multi-pass grids
+    the byte model per step (state read and written once per pass, plus one
+    potential read) over the step time."""
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype=dtype, equation=wl.equation, mass=wl.mass,
+                 charge=wl.charge, c=wl.c, hbar=wl.hbar)
+    g.set_potential(wl.V0)
+    if wl.equation == "dirac":
+        g.set_vector_potential(wl.abar_y)
+    else:
+        g.set_field(wl.ebar)
+    plan = list(g.autotune(5)) if (wl.equation == "schrodinger" and wl.ndim >= 2) else None
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psi = torch.from_numpy(wl.psi0).to("cuda").to(tdt).contiguous()
+    g.propagate(psi, 0, min(wl.nsteps, 10))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        g.propagate(psi, 0, wl.nsteps)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / (runs * wl.nsteps)
+    g.close()
+    del psi
+    torch.cuda.empty_cache()
+    npts = wl.npoints
+    s = 8 if dtype == "c64" else 16
+    v = 4 if dtype == "c64" else 8
+    if wl.equation == "dirac":
+        step_bytes = npts * (2 * 2 * 4 * s + v)  # row + column pass over 4 components, potential
+    elif wl.ndim == 3:
+        step_bytes = npts * (4 * 2 * s + v)  # x, y, z, y^-1 passes, potential
+    elif wl.ndim == 2:
+        step_bytes = npts * (2 * 2 * s + v)
+    else:
+        step_bytes = None  # 1-D: the line stays on chip for the whole run
+    out = {"grid": list(wl.n), "dtype": dtype, "steps_per_run": wl.nsteps, "ms_per_step": 1e3 * t,
+           "updates_per_s": npts / t, "plan": plan}
+    if step_bytes:
+        out["byte_model_gbs"] = step_bytes / t / 1e9
+        out["byte_model_frac"] = step_bytes / t / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def bench_configs():
+    from paper_1012_3911_amd import workloads as W
+
+    res = {}
+    for name, make, dtype, runs in (("1d_harmonic 1024 c128", lambda: W.harmonic_1d(), "c128", 5),
+                                    ("3d_wells 256^3 c64", lambda: W.wells_3d(), "c64", 2),
+                                    ("2d_dirac_softcore_laser 1024^2 c128", lambda: W.dirac_softcore_laser(), "c128", 2)):
+        res[name] = bench_config(make(), dtype, runs)
+        print("# %s %.4f ms/step  %.3e updates/s" % (name, res[name]["ms_per_step"], res[name]["updates_per_s"]),
+              file=sys.stderr, flush=True)
+    return res
+
+
 def bench_beyond_mall(steps=40):
     """2-D 4096 x 4096 complex128 (256 MiB of state, beyond the 256 MiB
     Infinity Cache once the potential is counted): the passes stream from HBM."""
@@ -379,6 +439,7 @@ def main():
     if not args.no_batch:
         out["beyond_mall"] = bench_beyond_mall()
         print("# 4096^2 c128 %.3f ms/step" % out["beyond_mall"]["ms_per_step"], file=sys.stderr, flush=True)
+        out["other_workloads"] = bench_configs()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         one = cpu_baseline(wl, args.cpu_seconds, threads=1)
