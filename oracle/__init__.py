@@ -154,6 +154,58 @@ def schrodinger(psi0, n, xmin, xmax, dt, V0, ebar=None, *, step0=0, nsteps=1, ma
     return (psi, norms) if return_norms else psi
 
 
+def autocorrelation(psi0, n, xmin, xmax, dt, V0, nsteps, *, mass=1.0, hbar=1.0):
+    """chi(t_j) = integral of conj(Psi(x, 0)) Psi(x, t_j), j = 0..nsteps-1, t_j = j dt
+    (the autocorrelation function of the paper's eigenstate section): the
+    oracle's own Strang steps in the time-independent potential V0, one at a
+    time, and its FP64 overlap after each.  Returns (chi, psi after nsteps)."""
+    psi = _c128(psi0).copy()
+    chi = np.zeros(nsteps, complex)
+    for j in range(nsteps):
+        chi[j] = overlap(psi0, psi, n, xmin, xmax)
+        psi = schrodinger(psi, n, xmin, xmax, dt, V0, None, step0=0, nsteps=1, mass=mass, hbar=hbar)
+    return chi, psi
+
+
+def spectrum(chi, dt, energies, hbar=1.0):
+    """Windowed Fourier transform of the autocorrelation (eigenstate section):
+    chi~(E) = integral_0^T chi(t) (1 - cos(2 pi t / T)) exp(i t E / hbar) dt with
+    T = len(chi) dt, as the rectangle rule over t_j = j dt (the window vanishes
+    at both ends, so it equals the trapezoid rule).  FP64, one energy at a time."""
+    chi = np.asarray(chi, complex)
+    S = len(chi)
+    t = dt * np.arange(S)
+    w = 1.0 - np.cos(2.0 * np.pi * np.arange(S) / S)
+    out = np.zeros(len(energies), complex)
+    for i, E in enumerate(energies):
+        out[i] = dt * np.sum(chi * w * np.exp(1j * t * E / hbar))
+    return out
+
+
+def eigenfunction(psi0, n, xmin, xmax, dt, V0, nsteps, E, *, mass=1.0, hbar=1.0):
+    """Psi_E(x) ~ integral_0^T Psi(x, t) (1 - cos(2 pi t / T)) exp(i E t / hbar) dt
+    (eigenstate section), the rectangle rule over the oracle's own steps,
+    normalised to dV sum |Psi_E|^2 = 1."""
+    psi = _c128(psi0).copy()
+    acc = np.zeros_like(psi)
+    for j in range(nsteps):
+        w = 1.0 - np.cos(2.0 * np.pi * j / nsteps)
+        acc += dt * w * np.exp(1j * E * j * dt / hbar) * psi
+        psi = schrodinger(psi, n, xmin, xmax, dt, V0, None, step0=0, nsteps=1, mass=mass, hbar=hbar)
+    return acc / np.sqrt(norm(acc, n, xmin, xmax))
+
+
+def peak_energy(energies, spec):
+    """Energy of the largest |spec| on a uniform grid, refined by the vertex of
+    the parabola through it and its two neighbours."""
+    a = np.abs(np.asarray(spec))
+    i = int(np.argmax(a))
+    i = min(max(i, 1), len(a) - 2)
+    y0, y1, y2 = a[i - 1], a[i], a[i + 1]
+    d = 0.5 * (y0 - y2) / (y0 - 2.0 * y1 + y2)
+    return float(energies[i] + d * (energies[1] - energies[0]))
+
+
 def schrodinger_adjoint(psi0, gT, n, xmin, xmax, dt, V0, ebar=None, *, step0=0, nsteps=1,
                         mass=1.0, hbar=1.0, want_dV0=True):
     """Gradient through ``nsteps`` forward steps from a stored FP64 trajectory.
