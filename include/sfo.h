@@ -122,6 +122,30 @@ sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index);
  * equals nsteps calls of sfo_step to rounding. */
 sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nsteps);
 
+/* Autocorrelation run of the eigenstate method (the paper's eigenstate
+ * section, first equation): advances psi in place by nsteps steps of the
+ * time-independent potential and writes chi_j = dV sum_x conj(psi_0(x))
+ * psi_j(x), j = 0..nsteps-1 (psi_0 the state on entry, psi_j after j steps)
+ * to chi_dev as FP64 (re, im) pairs: 2 * nsteps doubles of device memory the
+ * caller owns (may be NULL when nsteps is 0).  chi_j is formed inside the k-space pass of step j from its
+ * state right after the forward transform and the stored transform of the
+ * entry state (Parseval; exact because every step's first half factor is
+ * the same unitary diagonal), summed in FP64 in a fixed order.  2-D and 3-D
+ * Schroedinger grids (SFO_E_UNSUPPORTED otherwise) with no field table set
+ * (SFO_E_UNSUPPORTED: clear it with sfo_set_field(g, NULL, 0)).  The library
+ * keeps a state-sized reference buffer on the handle.  Asynchronous. */
+sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double *chi_dev);
+
+/* Windowed Fourier transform of an autocorrelation (the eigenstate section,
+ * second equation) as the rectangle rule over t_j = j dt, T = nsteps dt:
+ * out[2e], out[2e+1] = re, im of sum_j dt chi_j (1 - cos(2 pi j / nsteps))
+ * exp(i j dt E_e / hbar), e < nE, with dt and hbar of the grid.  chi_dev:
+ * 2 * nsteps doubles, energies_dev: nE doubles, out_dev: 2 * nE doubles, all
+ * device memory the caller owns; FP64.  Peaks of |out| mark eigenenergies.
+ * Asynchronous on the grid's stream. */
+sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const double *energies_dev, int32_t nE,
+                        double *out_dev);
+
 /* Reverse-mode gradient through sfo_propagate(g, psi0, step0, nsteps)
  * (Schroedinger only).  On entry psi holds psi(T) = the forward result and
  * g_vec holds 2 dL/dconj(psi(T)) (the complex-autograd convention) for a

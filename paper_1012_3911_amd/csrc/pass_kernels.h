@@ -442,7 +442,7 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
 template <typename R, int N, int RAD, int C, int NS>
 __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int64_t slab, int64_t stride,
                                          int64_t slab_stride, const TwEntry<R> *__restrict__ tw, const KinArgs &kin,
-                                         int mode, cx<R> *lds, int tid)
+                                         int mode, cx<R> *lds, double (*red)[3], int tid)
 {
     constexpr int RV = LineShape<N, RAD>::RV;
     const int c = tid % C, t = tid / C;
@@ -458,7 +458,30 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
         kcr = a.re * b.re - a.im * b.im;
         kci = a.re * b.im + a.im * b.re;
     }
-    col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode);
+    if (mode & M_CHI) {
+        // overlap of the transformed state with the reference (same layout), between the
+        // forward transform and the kinetic factor
+        col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & M_FWD);
+        constexpr int T = LineShape<N, RAD>::T;
+        const char *rb = (const char *)((const cx<R> *)kin.chi_ref + ubase);
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const cx<R> r = gload((const cx<R> *)(rb + (int64_t)m * T * stride * (int64_t)sizeof(cx<R>) + tb));
+            const cx<R> a = v[0][m];
+            acc[0] += (double)r.re * (double)a.re + (double)r.im * (double)a.im;
+            acc[1] += (double)r.re * (double)a.im - (double)r.im * (double)a.re;
+        }
+        block_sum3(acc, red);
+        if (tid == 0) {
+            const int64_t slot = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+            gstore1(kin.chi_part + 2 * slot, acc[0]);
+            gstore1(kin.chi_part + 2 * slot + 1, acc[1]);
+        }
+        col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & (M_KIN | M_INV));
+    } else {
+        col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode);
+    }
     // the offset is recomputed rather than held through the transforms
     __asm__ __volatile__("" : "+v"(tb));
     col_store<R, N, RAD, NS>(v, S, ubase, stride, tb);
@@ -470,6 +493,7 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
           int mode, GroupArgs<R> grp)
 {
     __shared__ cx<R> lds[ColMap<C>::slots(N)];
+    __shared__ double red[16][3];
     if (grp.probs) {
         const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.z]];
         S.p[0] = P.psi;
@@ -482,7 +506,7 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
     const unsigned G = gridDim.x * gridDim.y;
     unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
-    col_tile<R, N, RAD, C, NS>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds,
+    col_tile<R, N, RAD, C, NS>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds, red,
                                threadIdx.x);
 }
 

@@ -75,8 +75,11 @@ struct sfo_grid_s {
     double2 *one = nullptr;                        // {1, 0}
     double *red = nullptr;                         // reduction partials + result
     // adjoint scratch: moment partials per step boundary and row work-group
+    // (the autocorrelation run keeps its overlap partials here too)
     double *part = nullptr;
     int64_t part_cap = 0;
+    void *chi_ref = nullptr;  // autocorrelation: reference state in k-space
+    size_t chi_ref_bytes = 0;
     // kernel timing: event pairs per kernel kind while profiling is on
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
@@ -117,6 +120,7 @@ void free_grid(sfo_grid g)
     (void)hipFree(g->one);
     (void)hipFree(g->red);
     (void)hipFree(g->part);
+    (void)hipFree(g->chi_ref);
     delete g;
 }
 
@@ -305,29 +309,33 @@ sfo_status schro_xpass(sfo_grid g, void *psi, void *adj, int64_t sa, int64_t sb,
 
 // Forward/inverse transforms and the kinetic factor along the non-x axes.
 // mode: M_FWD, M_INV, M_KIN combinations (in the order FWD, KIN, INV).
-template <typename R> sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn)
+// chi_part: the k-space pass (the one with the kinetic factor) also forms
+// the overlap partials with g->chi_ref (M_CHI) into chi_part.
+template <typename R>
+sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, double *chi_part = nullptr)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
     const int ns = adj ? 2 : 1;
     const void *const *tw1 = (const void *const *)g->tw[1];
     const void *const *tw2 = (const void *const *)g->tw[2];
+    const int cmode = chi_part ? (mode | M_CHI) : mode;
     if (g->ndim == 2) {
-        KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn};
+        KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn, g->chi_ref, chi_part};
         HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-            return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, 1, 0, tw1, k, mode, g->st);
+            return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, 1, 0, tw1, k, cmode, g->st);
         }));
     } else {
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
         KinArgs none{g->one, g->one, g->one, 1, 1};
-        KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn};
+        KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn, g->chi_ref, chi_part};
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
                 return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
                                          g->st);
             }));
         HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
-            return launch_colpass<R>(col_shape(g, 2, ns), (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, mode, g->st);
+            return launch_colpass<R>(col_shape(g, 2, ns), (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, cmode, g->st);
         }));
         if (mode & M_INV)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
@@ -394,6 +402,56 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
                                 M_INV | M_PHASE | (more ? M_FWD : 0))))
             return s;
     }
+    return SFO_OK;
+}
+
+// Autocorrelation run (the eigenstate method): chi_j = dV sum_x conj(psi_0)
+// psi_j, j < nsteps, while psi advances nsteps steps.  With a
+// time-independent potential every step's first half factor P = exp(-i tau
+// V0 / 2 hbar) is the same unitary diagonal, so chi_j = dV sum conj(P psi_0)
+// (P psi_j) = (dV / Ntot) sum_k conj(F P psi_0)(F P psi_j) (Parseval,
+// unnormalised transform).  The k-space pass of step j holds F P psi_j right
+// after its forward transform and forms the overlap with the stored F P psi_0
+// there: FP64 partials per work-group, summed in slot order afterwards.
+template <typename R> sfo_status schro_autocorr(sfo_grid g, void *psi, int64_t nsteps, double *chi)
+{
+    if (nsteps == 0) return SFO_OK;
+    const int kax = g->ndim - 1;
+    const int64_t ncols = kax == 1 ? g->n[0] : g->n[0] * g->n[1];
+    const int nslots = (int)(ncols / kColVariants[col_shape(g, kax, 1)].cols);
+    const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
+    if (g->chi_ref_bytes < sbytes) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->chi_ref);
+        g->chi_ref = nullptr;
+        g->chi_ref_bytes = 0;
+        HIP_TRY(hipMalloc(&g->chi_ref, sbytes));
+        g->chi_ref_bytes = sbytes;
+    }
+    const int64_t need = 2 * (int64_t)nslots * nsteps;
+    if (g->part_cap < need) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->part);
+        g->part = nullptr;
+        g->part_cap = 0;
+        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
+        g->part_cap = need;
+    }
+    // reference F P psi_0: the run's first row pass and the forward transforms of the other axes
+    HIP_TRY(hipMemcpyAsync(g->chi_ref, psi, sbytes, hipMemcpyDeviceToDevice, g->st));
+    sfo_status s;
+    if ((s = schro_xpass<R>(g, g->chi_ref, nullptr, -1, 0, +1, M_PHASE | M_FWD))) return s;
+    if ((s = schro_colpasses<R>(g, g->chi_ref, nullptr, M_FWD, +1))) return s;
+    // the fused run, the k-space pass of step j writing the partials of step j
+    if ((s = schro_xpass<R>(g, psi, nullptr, -1, 0, +1, M_PHASE | M_FWD))) return s;
+    for (int64_t j = 0; j < nsteps; ++j) {
+        if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD | M_KIN | M_INV, +1, g->part + 2 * (int64_t)nslots * j)))
+            return s;
+        const bool more = j + 1 < nsteps;
+        if ((s = schro_xpass<R>(g, psi, nullptr, 0, more ? 0 : -1, +1, M_INV | M_PHASE | (more ? M_FWD : 0))))
+            return s;
+    }
+    HIP_TRY(launch_chi_sum(g->part, nslots, nsteps, g->dv / (double)g->ntot, chi, g->st));
     return SFO_OK;
 }
 
@@ -1302,6 +1360,27 @@ sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nstep
 }
 
 sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index) { return sfo_propagate(g, psi_dev, step_index, 1); }
+
+sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double *chi_dev)
+{
+    if (!g || !psi_dev || (!chi_dev && nsteps > 0)) return fail(SFO_E_INVALID, "null grid, state or output");
+    if (nsteps < 0) return fail(SFO_E_INVALID, "negative step count");
+    if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
+        return fail(SFO_E_UNSUPPORTED, "the autocorrelation run is built for 2-D and 3-D Schroedinger grids");
+    if (g->ebar_steps > 0)
+        return fail(SFO_E_UNSUPPORTED, "the autocorrelation run needs a time-independent potential: clear the field table");
+    return g->c128 ? schro_autocorr<double>(g, psi_dev, nsteps, chi_dev)
+                   : schro_autocorr<float>(g, psi_dev, nsteps, chi_dev);
+}
+
+sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const double *energies_dev, int32_t nE,
+                        double *out_dev)
+{
+    if (!g || !chi_dev || !energies_dev || !out_dev) return fail(SFO_E_INVALID, "null argument");
+    if (nsteps < 1 || nE < 0) return fail(SFO_E_INVALID, "need nsteps >= 1 and nE >= 0");
+    HIP_TRY(launch_spectrum(chi_dev, nsteps, g->d.dt, g->d.hbar, energies_dev, nE, out_dev, g->st));
+    return SFO_OK;
+}
 
 sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps, double *dL_debar_dev,
                        double *dL_dV0_dev)

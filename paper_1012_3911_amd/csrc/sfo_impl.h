@@ -16,6 +16,7 @@ enum : int {
     M_KIN = 8,    // momentum-space factor (column passes only)
     M_FWD = 4,    // forward transform along the pass axis (last for rows, first for columns)
     M_GRAD = 16,  // adjoint partials at a step boundary (row passes with two states)
+    M_CHI = 32,   // overlap with a reference k-space state after the forward transform (column passes)
 };
 
 // The states a pass transforms together: p[0] alone, or the state p[0] and
@@ -46,12 +47,17 @@ struct PhaseArgs {
 
 // Momentum-space factor of a column pass, for element e of column `col`:
 //   K = kA[col % nA] * kB[col / nA] * kL[e]   (conjugated if sgn < 0).
+// M_CHI: chi_part[2 slot + {0, 1}] = sum over the work-group's points of
+// conj(chi_ref) psi~ (FP64) right after the forward transform, slot = the
+// work-group's linear index; chi_ref has the state's layout.
 struct KinArgs {
     const double2 *kA;
     const double2 *kB;
     const double2 *kL;
     int nA;
     int sgn;
+    const void *chi_ref = nullptr;
+    double *chi_part = nullptr;
 };
 
 // Dirac real-space factor of a row pass (4 planes):
@@ -164,6 +170,14 @@ hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const
 // slot order (deterministic).
 hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int ndim, double scale, double *out,
                             hipStream_t st);
+
+// chi[2 j + {0, 1}] = scale * sum over the nslots partials of step j, in slot
+// order (deterministic), j < nsteps.
+hipError_t launch_chi_sum(const double *part, int nslots, int64_t nsteps, double scale, double *chi, hipStream_t st);
+
+// out[2 e + {0, 1}] = sum_j dt chi_j (1 - cos(2 pi j / nsteps)) exp(i j dt E_e / hbar), e < nE.
+hipError_t launch_spectrum(const double *chi, int64_t nsteps, double dt, double hbar, const double *E, int nE,
+                           double *out, hipStream_t st);
 
 // Number of work-groups (= gradient partial slots) of a row pass launch.
 template <typename R> int xpass_groups(int variant, int N, int64_t nrows);

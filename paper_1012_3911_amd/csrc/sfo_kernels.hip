@@ -76,6 +76,42 @@ __global__ void k_ebar_grad(const double *part, int nslots, int64_t nsteps, int 
     }
 }
 
+// Autocorrelation: chi_j = scale * sum over the slots of step j (slot order).
+__global__ void k_chi_sum(const double *part, int nslots, int64_t nsteps, double scale, double *chi)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nsteps; j += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < nslots; ++k) {
+            re += part[(j * nslots + k) * 2];
+            im += part[(j * nslots + k) * 2 + 1];
+        }
+        chi[2 * j] = re * scale;
+        chi[2 * j + 1] = im * scale;
+    }
+}
+
+// Windowed transform of the autocorrelation, one energy per thread: the sum
+// over steps in step order, window 1 - cos(2 pi j / nsteps), phase j dt E /
+// hbar (range-reduced FP64 sine and cosine).
+__global__ void k_spectrum(const double *chi, int64_t nsteps, double dt, double hbar, const double *E, int nE,
+                           double *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    const double w0 = 2.0 * 3.14159265358979323846 / (double)nsteps, a = dt * E[e] / hbar;
+    double re = 0.0, im = 0.0;
+    for (int64_t j = 0; j < nsteps; ++j) {
+        double sw, cw, s, c;
+        sincos_fp64(w0 * (double)j, sw, cw);
+        sincos_fp64(a * (double)j, s, c);
+        const double w = 1.0 - cw, xr = chi[2 * j], xi = chi[2 * j + 1];
+        re += w * (xr * c - xi * s);
+        im += w * (xr * s + xi * c);
+    }
+    out[2 * e] = dt * re;
+    out[2 * e + 1] = dt * im;
+}
+
 // ------------------------------------------------------------- reductions --
 template <typename R>
 __global__ void __launch_bounds__(256) k_norm_partial(const cx<R> *__restrict__ a, int64_t n, double *part)
@@ -259,6 +295,23 @@ hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int 
     const int64_t n = nsteps * ndim;
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_ebar_grad, dim3(blocks), dim3(256), 0, st, part, nslots, nsteps, ndim, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_sum(const double *part, int nslots, int64_t nsteps, double scale, double *chi, hipStream_t st)
+{
+    if (nsteps <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((nsteps + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_chi_sum, dim3(blocks), dim3(256), 0, st, part, nslots, nsteps, scale, chi);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(const double *chi, int64_t nsteps, double dt, double hbar, const double *E, int nE,
+                           double *out, hipStream_t st)
+{
+    if (nE <= 0 || nsteps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spectrum, dim3((unsigned)((nE + 63) / 64)), dim3(64), 0, st, chi, nsteps, dt, hbar, E, nE,
+                       out);
     return hipGetLastError();
 }
 

@@ -54,8 +54,8 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_set_vector_potential", "sfo_step", "sfo_propagate", "sfo_adjoint", "sfo_norm",
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
-           "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_last_error",
-           "sfo_version"]
+           "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
+           "sfo_spectrum", "sfo_last_error", "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 TIME_IN_STEP = 16  # or'ed into a kernel kind: time the pass within whole steps
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "sfo_profile_enable": [P, I32],
         "sfo_profile_read": [P, I32, P, P],
         "sfo_time_pass": [P, I32, I32, P],
+        "sfo_autocorrelation": [P, P, I64, P],
+        "sfo_spectrum": [P, P, I64, P, I32, P],
         "sfo_create_batch": [P, I32, P, ctypes.POINTER(P)],
         "sfo_destroy_batch": [P],
         "sfo_propagate_batch": [P, P, I64, I64],
@@ -207,6 +209,26 @@ class Grid:
 
     def propagate(self, psi, step0: int, nsteps: int):
         _check(_lib.sfo_propagate(self._h, self._state(psi), int(step0), int(nsteps)), "sfo_propagate")
+
+    def autocorrelation(self, psi, nsteps: int):
+        """Advance psi by nsteps steps (no field) and return chi_j = <psi_0|psi_j>,
+        j < nsteps, as a complex128 CUDA tensor."""
+        torch = _torch()
+        chi = torch.empty(2 * int(nsteps), dtype=torch.float64, device="cuda")
+        _check(_lib.sfo_autocorrelation(self._h, self._state(psi), int(nsteps),
+                                        ctypes.c_void_p(chi.data_ptr())), "sfo_autocorrelation")
+        return torch.view_as_complex(chi.view(-1, 2))
+
+    def spectrum(self, chi, energies):
+        """Windowed transform of an autocorrelation at the given energies (complex128 CUDA tensor)."""
+        torch = _torch()
+        c = torch.view_as_real(chi.to(torch.complex128)).contiguous().view(-1)
+        E = torch.as_tensor(energies, dtype=torch.float64, device="cuda").contiguous()
+        out = torch.empty(2 * E.numel(), dtype=torch.float64, device="cuda")
+        _check(_lib.sfo_spectrum(self._h, ctypes.c_void_p(c.data_ptr()), c.numel() // 2,
+                                 ctypes.c_void_p(E.data_ptr()), int(E.numel()),
+                                 ctypes.c_void_p(out.data_ptr())), "sfo_spectrum")
+        return torch.view_as_complex(out.view(-1, 2))
 
     def adjoint(self, psi, g, step0: int, nsteps: int, want_dV0: bool = True):
         torch = _torch()

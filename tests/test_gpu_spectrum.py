@@ -1,0 +1,99 @@
+"""GPU autocorrelation run and windowed spectrum (the paper's eigenstate
+section) against the oracle: chi_j per step (complex128 to 1e-11, complex64 to
+1e-5 of chi_0), the state after the run, the spectrum kernel, and the 2-D
+soft-core ground state the paper quotes for zeta = 0.791."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1012_3911_amd import workloads as W
+from gpu_util import make_grid, rel_l2, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _softcore(n, L, zeta=0.791):
+    axes = [-L + 2 * L / m * np.arange(m) for m in n]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")  # (z, y, x) order
+    r2 = sum(g ** 2 for g in grids)
+    V = -1.0 / np.sqrt(r2 + zeta ** 2)
+    psi0 = np.exp(-r2 / 2 - 0.3j * grids[-1]).astype(complex)  # a little momentum along x
+    return V, psi0
+
+
+def _wl(n, L, dt, nsteps):
+    V, psi0 = _softcore(n, L)
+    return W.Workload("chi", "schrodinger", tuple(n), (-L,) * len(n), (L,) * len(n), dt, nsteps, V, psi0)
+
+
+@pytest.mark.parametrize("dtype,n,nsteps,tol", [("c128", (128, 64), 120, 1e-11), ("c64", (128, 64), 120, 1e-5),
+                                                ("c128", (64, 64, 64), 12, 1e-11)])
+def test_autocorrelation_matches_oracle(dtype, n, nsteps, tol):
+    import torch
+
+    wl = _wl(n, 12.0, 0.05, nsteps)
+    g = make_grid(wl, dtype)
+    g.set_field(None)
+    psi = to_device(wl.psi0, dtype)
+    chi = g.autocorrelation(psi, nsteps).cpu().numpy()
+    torch.cuda.synchronize()
+    p0 = wl.psi0.astype(np.complex64).astype(complex) if dtype == "c64" else wl.psi0
+    ref, psi_ref = orc.autocorrelation(p0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, nsteps)
+    err = np.max(np.abs(chi - ref)) / abs(ref[0])
+    assert err < tol, err
+    assert rel_l2(psi.cpu().numpy(), psi_ref) < (1e-12 if dtype == "c128" else 1e-5)
+    g.close()
+
+
+def test_spectrum_kernel_matches_oracle():
+    wl = _wl((128, 64), 12.0, 0.05, 300)
+    g = make_grid(wl, "c128")
+    g.set_field(None)
+    psi = to_device(wl.psi0, "c128")
+    chi = g.autocorrelation(psi, wl.nsteps)
+    E = np.linspace(-1.0, 2.0, 257)
+    sp = g.spectrum(chi, E).cpu().numpy()
+    ref = orc.spectrum(chi.cpu().numpy(), wl.dt, E)
+    assert np.max(np.abs(sp - ref)) < 1e-11 * np.max(np.abs(ref))
+    g.close()
+
+
+def test_softcore_2d_ground_state():
+    """zeta = 0.791 in 2-D gives the 3-D Coulomb ground state energy -1/2
+    (the paper's statement); the GPU spectrum's lowest peak agrees with it and
+    with the oracle's spectrum of the same run."""
+    N, L, dt, S = 128, 20.0, 0.05, 2000
+    V, _ = _softcore((N, N), L)
+    x = -L + 2 * L / N * np.arange(N)
+    psi0 = np.exp(-0.5 * (x[:, None] ** 2 + x[None, :] ** 2))  # real Gaussian, no momentum
+    wl = W.Workload("gs", "schrodinger", (N, N), (-L, -L), (L, L), dt, S, V, psi0.astype(complex))
+    g = make_grid(wl, "c128")
+    g.set_field(None)
+    psi = to_device(wl.psi0, "c128")
+    chi = g.autocorrelation(psi, S)
+    E = np.linspace(-0.7, -0.3, 401)
+    peak = orc.peak_energy(E, g.spectrum(chi, E).cpu().numpy())
+    assert abs(peak + 0.5) < 0.01
+    ref, _ = orc.autocorrelation(wl.psi0, wl.n, wl.xmin, wl.xmax, dt, V, S)
+    assert abs(peak - orc.peak_energy(E, orc.spectrum(ref, dt, E))) < 1e-8
+    g.close()
+
+
+def test_autocorrelation_rejects():
+    from paper_1012_3911_amd import sfo
+
+    wl = _wl((64, 64), 8.0, 0.05, 4)
+    g = make_grid(wl, "c128")
+    psi = to_device(wl.psi0, "c128")
+    g.set_field(np.zeros((4, 2)))
+    with pytest.raises(sfo.SfoError):
+        g.autocorrelation(psi, 4)  # a field table is set
+    g.set_field(None)
+    g.autocorrelation(psi, 0)
+    g.close()
+    w1 = W.Workload("l", "schrodinger", (256,), (-5.0,), (5.0,), 0.01, 1, np.zeros(256), np.ones(256, complex))
+    g1 = make_grid(w1, "c128")
+    g1.set_field(None)
+    with pytest.raises(sfo.SfoError):
+        g1.autocorrelation(to_device(w1.psi0, "c128"), 4)
+    g1.close()
