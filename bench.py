@@ -261,6 +261,51 @@ def bench_configs():
     return res
 
 
+def bench_autocorrelation(runs=2):
+    """The eigenstate method on the 2048^2 complex64 grid of the main
+    workload with its field switched off: a 500-step autocorrelation run
+    (the overlap with the entry state fused into the k-space pass) against a
+    plain 500-step run, and the windowed spectrum at 2000 energies."""
+    import torch
+    from paper_1012_3911_amd import sfo, workloads as W
+
+    wl = W.softcore_2d_laser()
+    g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c64")
+    g.set_potential(wl.V0)
+    g.set_field(None)
+    g.autotune(5)
+    psi = torch.from_numpy(wl.psi0).to("cuda").to(torch.complex64).contiguous()
+    g.autocorrelation(psi, 10)
+    g.propagate(psi, 0, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        chi = g.autocorrelation(psi, wl.nsteps)
+    torch.cuda.synchronize()
+    t_chi = (time.perf_counter() - t0) / (runs * wl.nsteps)
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        g.propagate(psi, 0, wl.nsteps)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / (runs * wl.nsteps)
+    E = torch.linspace(-1.0, 1.0, 2000, dtype=torch.float64, device="cuda")
+    g.spectrum(chi, E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.spectrum(chi, E)
+    torch.cuda.synchronize()
+    t_spec = time.perf_counter() - t0
+    g.close()
+    del psi
+    torch.cuda.empty_cache()
+    npts = wl.npoints
+    step_bytes = npts * (2 * 2 * 8 + 4 + 8)  # two passes, potential, the reference read in the k-space pass
+    return {"grid": list(wl.n), "dtype": "c64", "steps_per_run": wl.nsteps, "ms_per_step": 1e3 * t_chi,
+            "updates_per_s": npts / t_chi, "ms_per_step_without_chi": 1e3 * t_plain,
+            "byte_model_gbs": step_bytes / t_chi / 1e9, "byte_model_frac": step_bytes / t_chi / 1e9 / HBM_PEAK_GBS,
+            "spectrum_ms_2000_energies": 1e3 * t_spec}
+
+
 def bench_beyond_mall(steps=40):
     """2-D 4096 x 4096 complex128 (256 MiB of state, beyond the 256 MiB
     Infinity Cache once the potential is counted): the passes stream from HBM."""
@@ -440,6 +485,10 @@ def main():
         out["beyond_mall"] = bench_beyond_mall()
         print("# 4096^2 c128 %.3f ms/step" % out["beyond_mall"]["ms_per_step"], file=sys.stderr, flush=True)
         out["other_workloads"] = bench_configs()
+        out["autocorrelation"] = bench_autocorrelation()
+        print("# autocorrelation 2048^2 c64 %.4f ms/step (plain run %.4f)" % (
+            out["autocorrelation"]["ms_per_step"], out["autocorrelation"]["ms_per_step_without_chi"]),
+            file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         one = cpu_baseline(wl, args.cpu_seconds, threads=1)

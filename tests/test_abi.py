@@ -87,4 +87,6 @@ def test_null_arguments(lib):
     assert lib.sfo_batch_set_graph(None, 1) == -1
     assert lib.sfo_batch_check(None) == -1
     assert lib.sfo_time_pass(None, 0, 10, None) == -1
+    assert lib.sfo_autocorrelation(None, None, 4, None) == -1
+    assert lib.sfo_spectrum(None, None, 4, None, 1, None) == -1
     assert lib.sfo_version().decode().startswith("sfo")
