@@ -439,7 +439,7 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
         for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
 }
 
-template <typename R, int N, int RAD, int C, int NS>
+template <typename R, int N, int RAD, int C, int NS, bool CHI>
 __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int64_t slab, int64_t stride,
                                          int64_t slab_stride, const TwEntry<R> *__restrict__ tw, const KinArgs &kin,
                                          int mode, cx<R> *lds, double (*red)[3], int tid)
@@ -458,9 +458,10 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
         kcr = a.re * b.re - a.im * b.im;
         kci = a.re * b.im + a.im * b.re;
     }
-    if (mode & M_CHI) {
+    if constexpr (CHI) {
         // overlap of the transformed state with the reference (same layout), between the
-        // forward transform and the kinetic factor
+        // forward transform and the kinetic factor (a kernel of its own: the
+        // extra code would otherwise cost the plain pass registers)
         col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & M_FWD);
         constexpr int T = LineShape<N, RAD>::T;
         const char *rb = (const char *)((const cx<R> *)kin.chi_ref + ubase);
@@ -487,7 +488,7 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
     col_store<R, N, RAD, NS>(v, S, ubase, stride, tb);
 }
 
-template <typename R, int N, int RAD, int C, int WPE, int NS>
+template <typename R, int N, int RAD, int C, int WPE, int NS, bool CHI = false>
 __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw, KinArgs kin,
           int mode, GroupArgs<R> grp)
@@ -506,8 +507,8 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
     const unsigned G = gridDim.x * gridDim.y;
     unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
-    col_tile<R, N, RAD, C, NS>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds, red,
-                               threadIdx.x);
+    col_tile<R, N, RAD, C, NS, CHI>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds, red,
+                                    threadIdx.x);
 }
 
 // ---------------------------------------------------------------- 1-D run --
@@ -725,9 +726,16 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
         // per-thread byte offsets within a work-group's lines are 32-bit
         if (((int64_t)(LineShape<N, cv.rad>::T - 1) * stride + cv.cols) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
             return hipErrorInvalidValue;
-        launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>,
-                      dim3((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup),
-                      dim3(cv.cols * LineShape<N, cv.rad>::T), st, ev, S, stride, slab_stride,
+        const dim3 grid((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup);
+        const dim3 block(cv.cols * LineShape<N, cv.rad>::T);
+        if constexpr (NS == 1) {
+            if (mode & M_CHI) {
+                launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, 1, true>, grid, block, st, ev, S, stride,
+                              slab_stride, (const TwEntry<R> *)tw, kin, mode, grp);
+                return hipGetLastError();
+            }
+        }
+        launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>, grid, block, st, ev, S, stride, slab_stride,
                       (const TwEntry<R> *)tw, kin, mode, grp);
         return hipGetLastError();
     }
