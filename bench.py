@@ -50,15 +50,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "cd15b9df221c5d3661296f4b7c03aae5cf16d71e75be5d029d92d7de81e08d55",
+    "sources_sha256": "807798215e397f8424670afb4d0e759beef7875b438f3997445abafd9dd345bb",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
     "row/0": (24724, 32768), "row/1": (24726, 32768), "row/2": (24719, 32768), "row/3": (24726, 32768),
     "row/4": (24722, 32768), "row/5": (24702, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
-    "row/8": (24686, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
+    "row/8": (24687, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
     "row/12": (24721, 32768), "row/13": (24702, 32768),
-    "column/0": (16662, 32832), "column/1": (16658, 32790), "column/2": (16660, 33327),
-    "column/4": (16658, 32784), "column/5": (16653, 33204), "column/7": (16767, 32813),
-    "column/8": (16636, 35790),
+    "column/0": (16663, 32843), "column/1": (16659, 32777), "column/2": (16660, 33295),
+    "column/4": (16650, 32779), "column/5": (16660, 33458), "column/7": (16771, 32798),
+    "column/8": (16629, 33989),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
 
