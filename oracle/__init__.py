@@ -58,10 +58,11 @@ def _load():
     lib.orc_schrodinger.argtypes = [I, P, P, P, D, D, D, P, P, P, I64, I64, I, P]
     lib.orc_schrodinger_adjoint.argtypes = [I, P, P, P, D, D, D, P, P, P, P, I64, I64, P, P]
     lib.orc_dirac2d.argtypes = [P, P, P, D, D, D, D, D, P, P, P, I64, I64, I]
+    lib.orc_schrodinger_velocity.argtypes = [I, P, P, P, D, D, D, D, P, P, P, P, I64, I64]
     lib.orc_num_threads.restype = I
     lib.orc_set_num_threads.argtypes = [I]
     for f in (lib.orc_fft, lib.orc_norm, lib.orc_overlap, lib.orc_schrodinger,
-              lib.orc_schrodinger_adjoint, lib.orc_dirac2d):
+              lib.orc_schrodinger_adjoint, lib.orc_dirac2d, lib.orc_schrodinger_velocity):
         f.restype = I
     _lib = lib
     return lib
@@ -204,6 +205,26 @@ def peak_energy(energies, spec):
     y0, y1, y2 = a[i - 1], a[i], a[i + 1]
     d = 0.5 * (y0 - y2) / (y0 - 2.0 * y1 + y2)
     return float(energies[i] + d * (energies[1] - energies[0]))
+
+
+def schrodinger_velocity(psi0, n, xmin, xmax, dt, V0, abar, a2bar, *, step0=0, nsteps=1, mass=1.0,
+                         hbar=1.0, charge=-1.0):
+    """Strang steps in the velocity gauge of the dipole approximation: the
+    kinetic factor exp(-i/(2 m hbar) [tau p^2 - 2 q p.Abar_n + q^2 A2bar_n])
+    (the momentum-space operator of eq. SE_K integrated over the step), the
+    potential half steps with tau V0 only.  ``abar``: (total_steps, ndim) step
+    integrals of A(t); ``a2bar``: (total_steps,) step integrals of |A(t)|^2."""
+    ndim, nn, lo, hi = _axes(n, xmin, xmax)
+    psi = _c128(psi0).copy()
+    v = np.ascontiguousarray(V0, dtype=np.float64)
+    a = np.ascontiguousarray(abar, dtype=np.float64)
+    a2 = np.ascontiguousarray(a2bar, dtype=np.float64)
+    assert v.size == psi.size and a.shape[1] == ndim and a.shape[0] >= step0 + nsteps and a2.size >= step0 + nsteps
+    rc = _load().orc_schrodinger_velocity(ndim, _ptr(nn), _ptr(lo), _ptr(hi), float(dt), float(mass), float(hbar),
+                                          float(charge), _ptr(v), _ptr(a), _ptr(a2), _ptr(psi), int(step0),
+                                          int(nsteps))
+    _check(rc, "schrodinger_velocity")
+    return psi
 
 
 def schrodinger_adjoint(psi0, gT, n, xmin, xmax, dt, V0, ebar=None, *, step0=0, nsteps=1,

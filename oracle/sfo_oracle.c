@@ -258,6 +258,11 @@ typedef struct {
     double dt, mass, hbar;
     const double *V0;
     const double *ebar; /* nsteps_total x ndim, or NULL */
+    /* velocity gauge (abar != NULL; ebar is then NULL): per step n the
+     * integrals abar[n ndim + a] = int A_a dt' and a2bar[n] = int |A|^2 dt'
+     * over the step, and the charge q */
+    const double *abar, *a2bar;
+    double charge;
 } schro;
 
 static double schro_theta(const schro *s, int64_t i, int64_t step)
@@ -279,7 +284,12 @@ static void schro_half(const schro *s, cplx *psi, int64_t step, int dir)
     }
 }
 
-static void schro_kinetic(const schro *s, cplx *psi, int dir)
+/* Kinetic factor of step `step` (the momentum-space operator of the
+ * dipole-approximation split, eq. SE_K): with p = hbar k,
+ *   exp(-(i/hbar) int_t^{t+tau} (p - q A(t'))^2 / (2m) dt')
+ *   = exp(-i/(2 m hbar) [tau p^2 - 2 q p.Abar_n + q^2 A2bar_n]),
+ * which is exp(-i hbar tau |k|^2 / (2m)) in the length gauge (A = 0). */
+static void schro_kinetic(const schro *s, cplx *psi, int64_t step, int dir)
 {
     const double inv = 1.0 / (double)s->g.ntot;
 #pragma omp parallel for schedule(static)
@@ -288,6 +298,11 @@ static void schro_kinetic(const schro *s, cplx *psi, int dir)
         grid_k(&s->g, i, k);
         double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
         double ph = s->hbar * s->dt * k2 / (2.0 * s->mass);
+        if (s->abar) {
+            double pa = 0.0;
+            for (int d = 0; d < s->g.ndim; d++) pa += s->hbar * k[d] * s->abar[step * s->g.ndim + d];
+            ph += (-2.0 * s->charge * pa + s->charge * s->charge * s->a2bar[step]) / (2.0 * s->mass * s->hbar);
+        }
         psi[i] *= cexp(-I * (double)dir * ph) * inv;
     }
 }
@@ -296,7 +311,7 @@ static int schro_step(const schro *s, cplx *psi, int64_t step, int dir)
 {
     schro_half(s, psi, step, dir);
     if (fft_nd(psi, s->g.ndim, s->g.n, -1)) return -1;
-    schro_kinetic(s, psi, dir);
+    schro_kinetic(s, psi, step, dir);
     if (fft_nd(psi, s->g.ndim, s->g.n, +1)) return -1;
     schro_half(s, psi, step, dir);
     return 0;
@@ -318,12 +333,39 @@ int orc_schrodinger(int ndim, const int64_t *n, const double *xmin, const double
     s.hbar = hbar;
     s.V0 = V0;
     s.ebar = ebar;
+    s.abar = s.a2bar = NULL;
+    s.charge = -1.0;
     if (norms) orc_norm(ndim, n, xmin, xmax, 1, psi, &norms[0]);
     for (int64_t j = 0; j < nsteps; j++) {
         int64_t step = (dir > 0) ? step0 + j : step0 + nsteps - 1 - j;
         if (schro_step(&s, psi, step, dir)) return -1;
         if (norms) orc_norm(ndim, n, xmin, xmax, 1, psi, &norms[j + 1]);
     }
+    return 0;
+}
+
+/* Velocity-gauge steps (no scalar field term): the potential half steps use
+ * tau V0 only, the kinetic factor carries the vector potential of the
+ * field through its per-step integrals abar (nsteps_total x ndim) and a2bar
+ * (nsteps_total).  Forward only. */
+int orc_schrodinger_velocity(int ndim, const int64_t *n, const double *xmin, const double *xmax, double dt,
+                             double mass, double hbar, double charge, const double *V0, const double *abar,
+                             const double *a2bar, cplx *psi, int64_t step0, int64_t nsteps)
+{
+    schro s;
+    if (grid_make(&s.g, ndim, n, xmin, xmax) || !V0 || !psi || !abar || !a2bar || nsteps < 0 || step0 < 0 ||
+        !(mass > 0) || !(hbar > 0))
+        return -1;
+    s.dt = dt;
+    s.mass = mass;
+    s.hbar = hbar;
+    s.V0 = V0;
+    s.ebar = NULL;
+    s.abar = abar;
+    s.a2bar = a2bar;
+    s.charge = charge;
+    for (int64_t j = 0; j < nsteps; j++)
+        if (schro_step(&s, psi, step0 + j, 1)) return -1;
     return 0;
 }
 
@@ -349,6 +391,8 @@ int orc_schrodinger_adjoint(int ndim, const int64_t *n, const double *xmin, cons
     s.hbar = hbar;
     s.V0 = V0;
     s.ebar = ebar;
+    s.abar = s.a2bar = NULL;
+    s.charge = -1.0;
     const int64_t N = s.g.ntot;
     cplx *traj = (cplx *)malloc(sizeof(cplx) * (size_t)N * (size_t)(nsteps + 1));
     if (!traj) return -2;
