@@ -107,8 +107,22 @@ sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev);
 /* Copy the per-step field integrals Ebar[step][axis] (host, FP64,
  * nsteps x ndim, axis x first) into a device table indexed by absolute step
  * number.  Steps beyond the table are an error at propagation time; with no
- * table the field is zero.  Schroedinger only. */
+ * table the field is zero.  Also releases velocity-gauge tables
+ * (sfo_set_vector_field).  Schroedinger only. */
 sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
+
+/* Velocity gauge of the dipole approximation (the split's momentum-space
+ * operator, eq. SE_K: exp(-(i/hbar) int (p - q A(t'))^2 / (2m) dt') per step,
+ * the potential half steps with tau V0 only).  abar_host: nsteps x ndim
+ * step integrals int A_a dt' (x first); a2bar_host: nsteps step integrals of
+ * |A|^2; FP64 host arrays, copied: the library builds per-step, per-axis
+ * kinetic tables (nsteps x (n[0] + n[1] + n[2]) complex FP64 on the device,
+ * at most 1 GiB: SFO_E_UNSUPPORTED beyond).  Replaces a length-gauge field
+ * table; sfo_set_field (any nsteps) in turn releases these tables.  nsteps
+ * = 0 clears.  2-D and 3-D Schroedinger grids (1-D: SFO_E_UNSUPPORTED);
+ * sfo_step / sfo_propagate use it; sfo_adjoint, sfo_autocorrelation and
+ * batches refuse a grid that has it (SFO_E_UNSUPPORTED). */
+sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps);
 
 /* Copy the per-step vector-potential integrals Abar_y[step][ix] (host,
  * FP64, nsteps x n[0]) of a field A = A_y(x, t) y_hat.  Dirac only. */

@@ -80,6 +80,9 @@ struct sfo_grid_s {
     int64_t part_cap = 0;
     void *chi_ref = nullptr;  // autocorrelation: reference state in k-space
     size_t chi_ref_bytes = 0;
+    // velocity gauge: per-step, per-axis kinetic factors (vsteps x n[a] each)
+    double2 *vtab[3] = {nullptr, nullptr, nullptr};
+    int64_t vsteps = 0;
     // kernel timing: event pairs per kernel kind while profiling is on
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
@@ -121,6 +124,7 @@ void free_grid(sfo_grid g)
     (void)hipFree(g->red);
     (void)hipFree(g->part);
     (void)hipFree(g->chi_ref);
+    for (int a = 0; a < 3; ++a) (void)hipFree(g->vtab[a]);
     delete g;
 }
 
@@ -234,6 +238,43 @@ sfo_status make_kinetic(sfo_grid g, int a)
     return SFO_OK;
 }
 
+// Velocity gauge (the dipole split's momentum-space operator with A(t)):
+// the kinetic factor of step n, exp(-i/(2 m hbar) int (p - q A)^2 dt') with
+// p = hbar k, factorises per axis as exp(-i [hbar tau k_a^2 / (2m) - q k_a
+// Abar_{n,a} / m]), times the global exp(-i q^2 A2bar_n / (2 m hbar)) and
+// 1/Ntot on axis 0.  Tables of every step, built in FP64 on the host.
+void release_vector_tables(sfo_grid g)
+{
+    for (int a = 0; a < 3; ++a) {
+        (void)hipFree(g->vtab[a]);
+        g->vtab[a] = nullptr;
+    }
+    g->vsteps = 0;
+}
+
+sfo_status make_vector_tables(sfo_grid g, const double *abar, const double *a2bar, int64_t nsteps)
+{
+    const double q = g->d.charge, m = g->d.mass, hb = g->d.hbar, tau = g->d.dt;
+    for (int a = 0; a < g->ndim; ++a) {
+        const int64_t n = g->n[a];
+        const double L = g->d.xmax[a] - g->d.xmin[a];
+        const double scale = a == 0 ? 1.0 / (double)g->ntot : 1.0;
+        std::vector<double2> h((size_t)(n * nsteps));
+        for (int64_t st = 0; st < nsteps; ++st)
+            for (int64_t j = 0; j < n; ++j) {
+                const double k = wavenumber(j, n, L);
+                double ph = hb * tau * k * k / (2.0 * m) - q * k * abar[st * g->ndim + a] / m;
+                if (a == 0) ph += q * q * a2bar[st] / (2.0 * m * hb);
+                h[(size_t)(st * n + j)].x = std::cos(ph) * scale;
+                h[(size_t)(st * n + j)].y = -std::sin(ph) * scale;
+            }
+        HIP_TRY(hipMalloc(&g->vtab[a], sizeof(double2) * h.size()));
+        HIP_TRY(hipMemcpy(g->vtab[a], h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
+    }
+    g->vsteps = nsteps;
+    return SFO_OK;
+}
+
 hipEvent_t prof_event(sfo_grid g)
 {
     if (!g->ev_pool.empty()) {
@@ -311,8 +352,10 @@ sfo_status schro_xpass(sfo_grid g, void *psi, void *adj, int64_t sa, int64_t sb,
 // mode: M_FWD, M_INV, M_KIN combinations (in the order FWD, KIN, INV).
 // chi_part: the k-space pass (the one with the kinetic factor) also forms
 // the overlap partials with g->chi_ref (M_CHI) into chi_part.
+// kstep: the step whose kinetic factor applies (velocity gauge: per-step tables).
 template <typename R>
-sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, double *chi_part = nullptr)
+sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, double *chi_part = nullptr,
+                           int64_t kstep = 0)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
@@ -320,15 +363,19 @@ sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, 
     const void *const *tw1 = (const void *const *)g->tw[1];
     const void *const *tw2 = (const void *const *)g->tw[2];
     const int cmode = chi_part ? (mode | M_CHI) : mode;
+    const bool vg = g->vsteps > 0;
+    const double2 *kx = vg ? g->vtab[0] + kstep * nx : g->kin[0];
+    const double2 *ky = vg ? g->vtab[1] + kstep * ny : g->kin[1];
+    const double2 *kz = vg && g->ndim == 3 ? g->vtab[2] + kstep * nz : g->kin[2];
     if (g->ndim == 2) {
-        KinArgs k{g->kin[0], g->one, g->kin[1], (int)nx, sgn, g->chi_ref, chi_part};
+        KinArgs k{kx, g->one, ky, (int)nx, sgn, g->chi_ref, chi_part};
         HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
             return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, 1, 0, tw1, k, cmode, g->st);
         }));
     } else {
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
         KinArgs none{g->one, g->one, g->one, 1, 1};
-        KinArgs k{g->kin[0], g->kin[1], g->kin[2], (int)nx, sgn, g->chi_ref, chi_part};
+        KinArgs k{kx, ky, kz, (int)nx, sgn, g->chi_ref, chi_part};
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
                 return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
@@ -352,6 +399,9 @@ sfo_status check_steps(const sfo_grid g, int64_t step0, int64_t nsteps)
     if (g->ebar_steps > 0 && step0 + nsteps > g->ebar_steps)
         return fail(SFO_E_INVALID, "steps %lld..%lld exceed the field table (%lld steps)", (long long)step0,
                     (long long)(step0 + nsteps - 1), (long long)g->ebar_steps);
+    if (g->vsteps > 0 && step0 + nsteps > g->vsteps)
+        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the vector-field table (%lld steps)", (long long)step0,
+                    (long long)(step0 + nsteps - 1), (long long)g->vsteps);
     if (g->d.equation == SFO_DIRAC && g->abar_steps > 0 && step0 + nsteps > g->abar_steps)
         return fail(SFO_E_INVALID, "steps %lld..%lld exceed the vector-potential table (%lld steps)",
                     (long long)step0, (long long)(step0 + nsteps - 1), (long long)g->abar_steps);
@@ -387,7 +437,7 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
             if ((s = schro_xpass<R>(g, psi, nullptr, -1, st, dir, M_PHASE))) return s;
             if ((s = schro_xpass<R>(g, psi, nullptr, -1, -1, dir, M_FWD))) return s;
             if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD, dir))) return s;
-            if ((s = schro_colpasses<R>(g, psi, nullptr, M_KIN, dir))) return s;
+            if ((s = schro_colpasses<R>(g, psi, nullptr, M_KIN, dir, nullptr, st))) return s;
             if ((s = schro_colpasses<R>(g, psi, nullptr, M_INV, dir))) return s;
             if ((s = schro_xpass<R>(g, psi, nullptr, -1, -1, dir, M_INV))) return s;
             if ((s = schro_xpass<R>(g, psi, nullptr, st, -1, dir, M_PHASE))) return s;
@@ -396,7 +446,7 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
     }
     if ((s = schro_xpass<R>(g, psi, nullptr, -1, step_of(0), dir, M_PHASE | M_FWD))) return s;
     for (int64_t j = 0; j < nsteps; ++j) {
-        if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD | M_KIN | M_INV, dir))) return s;
+        if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD | M_KIN | M_INV, dir, nullptr, step_of(j)))) return s;
         const bool more = j + 1 < nsteps;
         if ((s = schro_xpass<R>(g, psi, nullptr, step_of(j), more ? step_of(j + 1) : -1, dir,
                                 M_INV | M_PHASE | (more ? M_FWD : 0))))
@@ -1318,6 +1368,7 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "field table is for the Schroedinger equation");
     if (nsteps < 0 || (nsteps > 0 && !ebar_host)) return fail(SFO_E_INVALID, "bad field table");
     HIP_TRY(hipStreamSynchronize(g->st));
+    release_vector_tables(g);
     (void)hipFree(g->ebar_d);
     g->ebar_d = nullptr;
     g->ebar.assign(ebar_host, ebar_host + nsteps * g->ndim);
@@ -1330,6 +1381,34 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
         HIP_TRY(hipMemcpy(g->ebar_d, g->ebar.data(), bytes, hipMemcpyHostToDevice));
     }
     return SFO_OK;
+}
+
+sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "the vector field is for the Schroedinger equation");
+    if (nsteps < 0 || (nsteps > 0 && (!abar_host || !a2bar_host))) return fail(SFO_E_INVALID, "bad vector-field table");
+    if (nsteps > 0 && g->ndim < 2)
+        return fail(SFO_E_UNSUPPORTED, "the velocity gauge is built for 2-D and 3-D grids");
+    int64_t per = 0;
+    for (int a = 0; a < g->ndim; ++a) per += g->n[a];
+    if (nsteps > 0 && (double)nsteps * (double)per * sizeof(double2) > (double)(1ll << 30))
+        return fail(SFO_E_UNSUPPORTED, "vector-field tables of %lld steps exceed 1 GiB", (long long)nsteps);
+    for (int64_t i = 0; i < nsteps * g->ndim; ++i)
+        if (!std::isfinite(abar_host[i])) return fail(SFO_E_INVALID, "vector-field table holds a non-finite value");
+    for (int64_t i = 0; i < nsteps; ++i)
+        if (!std::isfinite(a2bar_host[i])) return fail(SFO_E_INVALID, "vector-field table holds a non-finite value");
+    HIP_TRY(hipStreamSynchronize(g->st));
+    release_vector_tables(g);
+    // the velocity gauge replaces the length-gauge field
+    (void)hipFree(g->ebar_d);
+    g->ebar_d = nullptr;
+    g->ebar.clear();
+    g->ebar_steps = 0;
+    if (nsteps == 0) return SFO_OK;
+    sfo_status s = make_vector_tables(g, abar_host, a2bar_host, nsteps);
+    if (s) release_vector_tables(g);
+    return s;
 }
 
 sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps)
@@ -1367,7 +1446,7 @@ sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double
     if (nsteps < 0) return fail(SFO_E_INVALID, "negative step count");
     if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
         return fail(SFO_E_UNSUPPORTED, "the autocorrelation run is built for 2-D and 3-D Schroedinger grids");
-    if (g->ebar_steps > 0)
+    if (g->ebar_steps > 0 || g->vsteps > 0)
         return fail(SFO_E_UNSUPPORTED, "the autocorrelation run needs a time-independent potential: clear the field table");
     return g->c128 ? schro_autocorr<double>(g, psi_dev, nsteps, chi_dev)
                    : schro_autocorr<float>(g, psi_dev, nsteps, chi_dev);
@@ -1390,6 +1469,7 @@ sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, in
     sfo_status s = check_steps(g, step0, nsteps);
     if (s) return s;
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the Schroedinger equation");
+    if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the length gauge");
     return g->c128 ? schro_adjoint<double>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev)
                    : schro_adjoint<float>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev);
 }
@@ -1536,6 +1616,7 @@ sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stre
         if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "grid %d: batches hold Schroedinger grids", i);
         if (g->c128 != c128) return fail(SFO_E_INVALID, "grid %d: every grid of a batch has the same dtype", i);
         if (g->ndim > 2) return fail(SFO_E_UNSUPPORTED, "grid %d: batches hold 1-D and 2-D grids", i);
+        if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "grid %d: batches run in the length gauge", i);
     }
     sfo_batch b = new sfo_batch_s;
     b->grids.assign(grids, grids + count);

@@ -55,7 +55,7 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
            "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
-           "sfo_spectrum", "sfo_last_error", "sfo_version"]
+           "sfo_spectrum", "sfo_set_vector_field", "sfo_last_error", "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 TIME_IN_STEP = 16  # or'ed into a kernel kind: time the pass within whole steps
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "sfo_time_pass": [P, I32, I32, P],
         "sfo_autocorrelation": [P, P, I64, P],
         "sfo_spectrum": [P, P, I64, P, I32, P],
+        "sfo_set_vector_field": [P, P, P, I64],
         "sfo_create_batch": [P, I32, P, ctypes.POINTER(P)],
         "sfo_destroy_batch": [P],
         "sfo_propagate_batch": [P, P, I64, I64],
@@ -193,6 +194,18 @@ class Grid:
         if e.ndim != 2 or e.shape[1] != self.ndim:
             raise ValueError("ebar must have shape (nsteps, %d)" % self.ndim)
         _check(_lib.sfo_set_field(self._h, e.ctypes.data_as(ctypes.c_void_p), e.shape[0]), "sfo_set_field")
+
+    def set_vector_field(self, abar: Optional[np.ndarray], a2bar: Optional[np.ndarray] = None):
+        """Velocity gauge: per-step integrals of A(t) (nsteps, ndim) and of |A|^2 (nsteps,)."""
+        if abar is None:
+            _check(_lib.sfo_set_vector_field(self._h, None, None, 0), "sfo_set_vector_field")
+            return
+        a = np.ascontiguousarray(abar, dtype=np.float64)
+        a2 = np.ascontiguousarray(a2bar, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != self.ndim or a2.shape != (a.shape[0],):
+            raise ValueError("abar must have shape (nsteps, %d) and a2bar (nsteps,)" % self.ndim)
+        _check(_lib.sfo_set_vector_field(self._h, a.ctypes.data_as(ctypes.c_void_p),
+                                         a2.ctypes.data_as(ctypes.c_void_p), a.shape[0]), "sfo_set_vector_field")
 
     def set_vector_potential(self, abar_y: Optional[np.ndarray]):
         if abar_y is None:
