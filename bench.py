@@ -306,6 +306,49 @@ def bench_autocorrelation(runs=2):
             "spectrum_ms_2000_energies": 1e3 * t_spec}
 
 
+def bench_overall(steps=128, reps=3):
+    """The paper's "overall" figure: the time to propagate `steps` steps
+    including the copies of the state from host memory before the first step
+    and back after the last, on the 2048^2 complex64 workload; pinned and
+    pageable host buffers.  Context only: `value` has the state resident."""
+    import numpy as np
+    import torch
+    from paper_1012_3911_amd import sfo, workloads as W
+
+    wl = W.softcore_2d_laser()
+    g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c64")
+    g.set_potential(wl.V0)
+    g.set_field(wl.ebar)
+    g.autotune(5)
+    dev = torch.empty(wl.psi0.shape, dtype=torch.complex64, device="cuda")
+    out = {"grid": list(wl.n), "dtype": "c64", "steps": steps}
+    for kind in ("pinned", "pageable"):
+        host = torch.from_numpy(wl.psi0.astype(np.complex64))
+        if kind == "pinned":
+            host = host.pin_memory()
+        back = torch.empty_like(host, pin_memory=(kind == "pinned"))
+        best = None
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dev.copy_(host, non_blocking=True)
+            g.propagate(dev, 0, steps)
+            back.copy_(dev, non_blocking=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        out[kind] = {"ms": 1e3 * best, "updates_per_s": wl.npoints * steps / best}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.propagate(dev, 0, steps)
+    torch.cuda.synchronize()
+    out["resident_ms"] = 1e3 * (time.perf_counter() - t0)
+    g.close()
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_beyond_mall(steps=40):
     """2-D 4096 x 4096 complex128 (256 MiB of state, beyond the 256 MiB
     Infinity Cache once the potential is counted): the passes stream from HBM."""
@@ -485,6 +528,10 @@ def main():
         out["beyond_mall"] = bench_beyond_mall()
         print("# 4096^2 c128 %.3f ms/step" % out["beyond_mall"]["ms_per_step"], file=sys.stderr, flush=True)
         out["other_workloads"] = bench_configs()
+        out["overall_with_transfers"] = bench_overall()
+        print("# overall 128 steps incl. host copies: pinned %.2f ms, pageable %.2f ms, resident %.2f ms" % (
+            out["overall_with_transfers"]["pinned"]["ms"], out["overall_with_transfers"]["pageable"]["ms"],
+            out["overall_with_transfers"]["resident_ms"]), file=sys.stderr, flush=True)
         out["autocorrelation"] = bench_autocorrelation()
         print("# autocorrelation 2048^2 c64 %.4f ms/step (plain run %.4f)" % (
             out["autocorrelation"]["ms_per_step"], out["autocorrelation"]["ms_per_step_without_chi"]),
