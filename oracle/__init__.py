@@ -59,10 +59,11 @@ def _load():
     lib.orc_schrodinger_adjoint.argtypes = [I, P, P, P, D, D, D, P, P, P, P, I64, I64, P, P]
     lib.orc_dirac2d.argtypes = [P, P, P, D, D, D, D, D, P, P, P, I64, I64, I]
     lib.orc_schrodinger_velocity.argtypes = [I, P, P, P, D, D, D, D, P, P, P, P, I64, I64]
+    lib.orc_dirac1d.argtypes = [I64, D, D, D, D, D, D, D, P, P, P, I64, I64]
     lib.orc_num_threads.restype = I
     lib.orc_set_num_threads.argtypes = [I]
     for f in (lib.orc_fft, lib.orc_norm, lib.orc_overlap, lib.orc_schrodinger,
-              lib.orc_schrodinger_adjoint, lib.orc_dirac2d, lib.orc_schrodinger_velocity):
+              lib.orc_schrodinger_adjoint, lib.orc_dirac2d, lib.orc_schrodinger_velocity, lib.orc_dirac1d):
         f.restype = I
     _lib = lib
     return lib
@@ -248,6 +249,26 @@ def schrodinger_adjoint(psi0, gT, n, xmin, xmax, dt, V0, ebar=None, *, step0=0, 
                                          _ptr(dv) if dv is not None else None)
     _check(rc, "schrodinger_adjoint")
     return g, de, dv
+
+
+def dirac1d(psi0, n, xmin, xmax, dt, V0, abar=None, *, step0=0, nsteps=1, mass=1.0, charge=-1.0,
+            c=137.036, hbar=1.0):
+    """Strang steps of the 1-D two-component Dirac equation, 2-spinor of shape
+    (2, n).  ``abar`` has shape (total_steps, n): the step integral of A_1(x, t)."""
+    n = int(n[0]) if hasattr(n, "__len__") else int(n)
+    lo = float(xmin[0]) if hasattr(xmin, "__len__") else float(xmin)
+    hi = float(xmax[0]) if hasattr(xmax, "__len__") else float(xmax)
+    psi = _c128(psi0).copy()
+    assert psi.shape == (2, n)
+    v = np.ascontiguousarray(V0, dtype=np.float64)
+    a = None
+    if abar is not None:
+        a = np.ascontiguousarray(abar, dtype=np.float64)
+        assert a.shape[1] == n and a.shape[0] >= step0 + nsteps
+    rc = _load().orc_dirac1d(n, lo, hi, float(dt), float(mass), float(charge), float(c), float(hbar), _ptr(v),
+                             _ptr(a) if a is not None else None, _ptr(psi), int(step0), int(nsteps))
+    _check(rc, "dirac1d")
+    return psi
 
 
 def dirac2d(psi0, n, xmin, xmax, dt, V0, abar_y=None, *, step0=0, nsteps=1, mass=1.0,

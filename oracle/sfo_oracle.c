@@ -540,6 +540,54 @@ int orc_dirac2d(const int64_t *n, const double *xmin, const double *xmax, double
     return 0;
 }
 
+/* ------------------------------------------------------------ Dirac 1D --
+ * Two-component Dirac equation on a line (the paper's one-dimensional Dirac
+ * representation: alpha_1 = sigma_x, beta = sigma_z), 2-spinor stored as two
+ * planes [2][N].  Real-space half step: exp(-i tau V0 / (2 hbar)) (cos a +
+ * i sin a alpha_1), a = (1/2) q c Abar_1(x) / hbar (the one-dimensional form
+ * of the interaction operator, delta = 1/2); momentum-space step: exp(-i tau
+ * H(p) / hbar) / N with H(p) = c p alpha_1 + m c^2 beta, written as
+ * cos(E tau/hbar) - i sin(E tau/hbar) H(p) / E since H(p)^2 = E^2. */
+int orc_dirac1d(int64_t n, double xmin, double xmax, double dt, double mass, double charge, double c,
+                double hbar, const double *V0, const double *abar, cplx *psi, int64_t step0, int64_t nsteps)
+{
+    grid g;
+    int64_t nn[1] = {n};
+    double lo[1] = {xmin}, hi[1] = {xmax};
+    if (grid_make(&g, 1, nn, lo, hi) || !V0 || !psi || nsteps < 0 || step0 < 0 || !(c > 0) || !(hbar > 0))
+        return -1;
+    const double mc2 = mass * c * c, inv = 1.0 / (double)n;
+    cplx *p0 = psi, *p1 = psi + n;
+    for (int64_t j = 0; j < nsteps; j++) {
+        const int64_t step = step0 + j;
+        for (int half = 0; half < 2; half++) {
+            for (int64_t i = 0; i < n; i++) {
+                const double a = abar ? 0.5 * charge * c * abar[step * n + i] / hbar : 0.0;
+                const cplx ph = cexp(-I * dt * V0[i] / (2.0 * hbar));
+                const cplx u = p0[i], v = p1[i];
+                p0[i] = ph * (cos(a) * u + I * sin(a) * v);
+                p1[i] = ph * (I * sin(a) * u + cos(a) * v);
+            }
+            if (half == 1) break;
+            if (fft_nd(p0, 1, g.n, -1) || fft_nd(p1, 1, g.n, -1)) return -1;
+            for (int64_t i = 0; i < n; i++) {
+                double k[3];
+                grid_k(&g, i, k);
+                const double p = hbar * k[0];
+                const double E = sqrt(mc2 * mc2 + c * c * p * p);
+                const double ct = cos(E * dt / hbar), st = sin(E * dt / hbar);
+                /* cos - i sin/E [[mc2, c p], [c p, -mc2]] */
+                const cplx u00 = ct - I * st * mc2 / E, u01 = -I * st * c * p / E, u11 = ct + I * st * mc2 / E;
+                const cplx u = p0[i], v = p1[i];
+                p0[i] = (u00 * u + u01 * v) * inv;
+                p1[i] = (u01 * u + u11 * v) * inv;
+            }
+            if (fft_nd(p0, 1, g.n, +1) || fft_nd(p1, 1, g.n, +1)) return -1;
+        }
+    }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
