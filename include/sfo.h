@@ -16,7 +16,10 @@
  *                 a = q c Abar_y(x)/(2 hbar)              (eq. exp_alpha),
  *     U~_A2(1)  = cos(E tau/hbar) - i sin(E tau/hbar) H(hbar k)/E,
  *                 H = c alpha.p + m c^2 beta, E = sqrt(m^2c^4 + c^2 p^2)
- *                 (eq. U_A_2_DE, closed form of its diagonalisation).
+ *                 (eq. U_A_2_DE, closed form of its diagonalisation);
+ *   - Dirac, d = 1, 2-spinor (alpha_1 = sigma_x, beta = sigma_z): the same
+ *     with alpha_1 and a = q c Abar_1(x)/(2 hbar), Abar_1 the step integral
+ *     of the line's vector potential A_1(x, t).
  * Ebar_n = Int_{t_n}^{t_n+tau} E(t') dt' and Abar_n = Int A_y dt' are step
  * integrals supplied by the caller; both half steps of step n use the same
  * integral (eq. U_split).  The DFT is unnormalised forward,
@@ -28,7 +31,7 @@
  *   - A state is a contiguous device array, layout [comp][z][y][x] with x
  *     fastest (n[0] is the x size), complex64 (interleaved float re, im)
  *     or complex128 (interleaved double re, im) per desc.dtype; comp = 4
- *     for Dirac, 1 otherwise.  The caller owns every state buffer.
+ *     for 2-D Dirac, 2 for 1-D Dirac, 1 otherwise.  The caller owns every state buffer.
  *   - x_j = xmin + j dx, dx = (xmax - xmin)/n: the box is periodic and the
  *     right end is excluded.
  *   - All work is enqueued on the stream given at creation and is
@@ -70,7 +73,7 @@ enum {
 };
 
 typedef struct {
-    int32_t ndim;      /* 1, 2 or 3 (Dirac: 2) */
+    int32_t ndim;      /* 1, 2 or 3 (Dirac: 1 or 2) */
     int64_t n[3];      /* points per axis, x first; powers of two, 1-D 64..8192, 2-D/3-D 64..4096,
                           at most 2^35 bytes (32 GiB) per state component */
     double xmin[3];    /* box per axis, x first */
@@ -125,7 +128,8 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
 sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps);
 
 /* Copy the per-step vector-potential integrals Abar_y[step][ix] (host,
- * FP64, nsteps x n[0]) of a field A = A_y(x, t) y_hat.  Dirac only. */
+ * FP64, nsteps x n[0]) of a field A = A_y(x, t) y_hat (2-D; in 1-D the
+ * line's own component A_1(x, t)).  Dirac only. */
 sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps);
 
 /* One un-merged Strang step number `step_index` applied in place to psi. */

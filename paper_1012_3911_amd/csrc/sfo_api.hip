@@ -80,6 +80,7 @@ struct sfo_grid_s {
     int64_t part_cap = 0;
     void *chi_ref = nullptr;  // autocorrelation: reference state in k-space
     size_t chi_ref_bytes = 0;
+    double2 *du = nullptr;  // 1-D Dirac: U00, U01, U11 of the momentum-space step per k
     // velocity gauge: per-step, per-axis kinetic factors (vsteps x n[a] each)
     double2 *vtab[3] = {nullptr, nullptr, nullptr};
     int64_t vsteps = 0;
@@ -125,6 +126,7 @@ void free_grid(sfo_grid g)
     (void)hipFree(g->part);
     (void)hipFree(g->chi_ref);
     for (int a = 0; a < 3; ++a) (void)hipFree(g->vtab[a]);
+    (void)hipFree(g->du);
     delete g;
 }
 
@@ -235,6 +237,29 @@ sfo_status make_kinetic(sfo_grid g, int a)
     HIP_TRY(hipMemcpy(g->kin[a], h.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&g->kvec[a], sizeof(double) * n));
     HIP_TRY(hipMemcpy(g->kvec[a], kv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    return SFO_OK;
+}
+
+// 1-D Dirac (alpha_1 = sigma_x, beta = sigma_z): the momentum-space step
+// exp(-i tau H(p) / hbar) / N, H(p) = c p sigma_x + m c^2 sigma_z, p = hbar
+// k, is cos(E tau / hbar) - i sin(E tau / hbar) H(p) / E since H^2 = E^2
+// (E = sqrt(m^2 c^4 + c^2 p^2)); stored as U00, U01 (= U10), U11 per k.
+sfo_status make_dirac1d_kinetic(sfo_grid g)
+{
+    const int64_t n = g->n[0];
+    const double L = g->d.xmax[0] - g->d.xmin[0];
+    const double c = g->d.c, mc2 = g->d.mass * c * c, hb = g->d.hbar, tau = g->d.dt, inv = 1.0 / (double)n;
+    std::vector<double2> h((size_t)(3 * n));
+    for (int64_t j = 0; j < n; ++j) {
+        const double p = hb * wavenumber(j, n, L);
+        const double E = std::sqrt(mc2 * mc2 + c * c * p * p);
+        const double ct = std::cos(E * tau / hb), st = std::sin(E * tau / hb);
+        h[(size_t)(3 * j)] = {ct * inv, -st * mc2 / E * inv};
+        h[(size_t)(3 * j + 1)] = {0.0, -st * c * p / E * inv};
+        h[(size_t)(3 * j + 2)] = {ct * inv, st * mc2 / E * inv};
+    }
+    HIP_TRY(hipMalloc(&g->du, sizeof(double2) * h.size()));
+    HIP_TRY(hipMemcpy(g->du, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
     return SFO_OK;
 }
 
@@ -969,6 +994,21 @@ template <typename R> sfo_status dirac_colpass(sfo_grid g, void *psi, int mode, 
 template <typename R> sfo_status dirac_run(sfo_grid g, void *psi, int64_t step0, int64_t nsteps, int dir)
 {
     if (nsteps == 0) return SFO_OK;
+    if (g->ndim == 1) {
+        // the whole run of the line in one work-group (forward steps only)
+        if (dir != 1) return fail(SFO_E_UNSUPPORTED, "1-D Dirac runs forward");
+        Dirac1DArgs a{};
+        a.u = g->du;
+        a.abar = g->abar_steps ? g->abar_d : nullptr;
+        a.step0 = step0;
+        a.nsteps = nsteps;
+        a.aV_half = g->d.dt / (2.0 * g->d.hbar);
+        a.aA = 0.5 * g->d.charge * g->d.c / g->d.hbar;
+        HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
+            return launch_dirac1d<R>((int)g->n[0], (cx<R> *)psi, g->V0, (const void *const *)g->tw[0], a, g->st);
+        }));
+        return SFO_OK;
+    }
     auto step_of = [&](int64_t s) { return dir > 0 ? step0 + s : step0 + nsteps - 1 - s; };
     sfo_status s;
     if (g->d.flags & SFO_UNFUSED) {
@@ -1279,8 +1319,8 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     if (d.dtype != SFO_C64 && d.dtype != SFO_C128) return fail(SFO_E_INVALID, "unknown dtype %d", d.dtype);
     if (!(d.dt > 0) || !std::isfinite(d.dt)) return fail(SFO_E_INVALID, "dt must be positive and finite");
     if (!(d.hbar > 0) || !(d.mass > 0)) return fail(SFO_E_INVALID, "hbar and mass must be positive");
-    if (d.equation == SFO_DIRAC && (d.ndim != 2 || !(d.c > 0)))
-        return fail(SFO_E_INVALID, "Dirac needs ndim == 2 and c > 0");
+    if (d.equation == SFO_DIRAC && (d.ndim > 2 || !(d.c > 0)))
+        return fail(SFO_E_INVALID, "Dirac needs ndim 1 or 2 and c > 0");
     int64_t ntot = 1;
     for (int a = 0; a < d.ndim; ++a) {
         if (!is_pow2(d.n[a])) return fail(SFO_E_INVALID, "n[%d] = %lld is not a power of two", a, (long long)d.n[a]);
@@ -1309,7 +1349,7 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     g->d = d;
     g->st = (hipStream_t)hip_stream;
     g->ndim = d.ndim;
-    g->ncomp = d.equation == SFO_DIRAC ? 4 : 1;
+    g->ncomp = d.equation == SFO_DIRAC ? (d.ndim == 1 ? 2 : 4) : 1;
     g->ntot = ntot;
     g->c128 = d.dtype == SFO_C128;
     g->dv = 1.0;
@@ -1326,6 +1366,7 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     auto guard = [&](sfo_status r) { if (r != SFO_OK) { free_grid(g); } return r; };
     for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_twiddles(g, a);
     for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_kinetic(g, a);
+    if (s == SFO_OK && d.equation == SFO_DIRAC && d.ndim == 1) s = make_dirac1d_kinetic(g);
     if (s != SFO_OK) return guard(s);
     const double2 one = {1.0, 0.0};
     hipError_t he = hipMalloc(&g->one, sizeof(double2));

@@ -215,6 +215,114 @@ hipError_t launch_dirac_colpass(int N, cx<R> *psi, int nx, int64_t plane, const 
 #undef CALL
 }
 
+// ------------------------------------------------------------- 1-D Dirac --
+// The whole run of one line in one work-group: both components in registers
+// (cyclic layout), transformed one after the other through the same LDS
+// region; the real-space factor exp(-i th) (cos a + i sin a sigma_x) and the
+// momentum-space 2x2 factor are applied in FP64 with one rounding.
+template <typename R, typename VT, int N, int RAD>
+__global__ void __launch_bounds__((LineShape<N, RAD>::T))
+    k_dirac1d_run(cx<R> *__restrict__ psi, const VT *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
+                  Dirac1DArgs a)
+{
+    using Sh = LineShape<N, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    __shared__ cx<R> sh[RowMap<R, RAD>::slots(N)];
+    const int t = threadIdx.x;
+    cx<R> v[2][RV];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) v[q][m] = gload(psi + (int64_t)q * N + t + m * T);
+    auto abar = [&](int64_t st, int x) { return a.abar ? a.abar[st * N + x] : 0.0; };
+    // halves of steps sa and sb (sb < 0: one half)
+    auto potential = [&](int64_t sa, int64_t sb) {
+        const double w = sb >= 0 ? 2.0 : 1.0;
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            // an opaque index pins this point's table reads here (they do not
+            // depend on the state; the compiler would issue them all at once)
+            int x = t + m * T;
+            __asm__ __volatile__("" : "+v"(x));
+            const double th = w * a.aV_half * ldv(V0 + x);
+            const double aa = a.aA * (abar(sa, x) + (sb >= 0 ? abar(sb, x) : 0.0));
+            double s, c, sa_, ca;
+            sincos_fp64(th, s, c);
+            sincos_fp64(aa, sa_, ca);
+            const double ur = v[0][m].re, ui = v[0][m].im, vr = v[1][m].re, vi = v[1][m].im;
+            // (cos a u + i sin a v, i sin a u + cos a v), then times exp(-i th) = (c - i s)
+            const double pr = ca * ur - sa_ * vi, pi = ca * ui + sa_ * vr;
+            const double qr = ca * vr - sa_ * ui, qi = ca * vi + sa_ * ur;
+            v[0][m] = {(R)(c * pr + s * pi), (R)(c * pi - s * pr)};
+            v[1][m] = {(R)(c * qr + s * qi), (R)(c * qi - s * qr)};
+            if ((m & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    if (a.nsteps > 0) potential(a.step0, -1);
+#pragma unroll 1
+    for (int64_t s = 0; s < a.nsteps; ++s) {
+        __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < 2; ++q) fft_line<R, N, RAD, -1, RowMap<R, RAD>>(v[q], sh, t, tw);
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            int k = t + m * T;
+            __asm__ __volatile__("" : "+v"(k));
+            const double2 u00 = a.u[3 * k], u01 = a.u[3 * k + 1], u11 = a.u[3 * k + 2];
+            const double ur = v[0][m].re, ui = v[0][m].im, vr = v[1][m].re, vi = v[1][m].im;
+            v[0][m] = {(R)(u00.x * ur - u00.y * ui + u01.x * vr - u01.y * vi),
+                       (R)(u00.x * ui + u00.y * ur + u01.x * vi + u01.y * vr)};
+            v[1][m] = {(R)(u01.x * ur - u01.y * ui + u11.x * vr - u11.y * vi),
+                       (R)(u01.x * ui + u01.y * ur + u11.x * vi + u11.y * vr)};
+            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) fft_line<R, N, RAD, +1, RowMap<R, RAD>>(v[q], sh, t, tw);
+        const bool more = s + 1 < a.nsteps;
+        potential(a.step0 + s, more ? a.step0 + s + 1 : -1);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < RV; ++m) gstore(psi + (int64_t)q * N + t + m * T, v[q][m]);
+}
+
+// tws[0], tws[1]: the line's stage twiddles for radix 8 and 16.  Long lines
+// use radix 8 (more threads, half the registers per thread for the two
+// components).
+template <typename R, int N>
+static hipError_t dirac1d_n(cx<R> *psi, const void *V0, const void *const *tws, const Dirac1DArgs &a,
+                            hipStream_t st)
+{
+    using VT = typename std::conditional<sizeof(R) == 4, float, double>::type;
+    constexpr int RAD = N >= 4096 ? 8 : 16;
+    hipLaunchKernelGGL((k_dirac1d_run<R, VT, N, RAD>), dim3(1), dim3(LineShape<N, RAD>::T), 0, st, psi,
+                       (const VT *)V0, (const TwEntry<R> *)tws[RAD == 8 ? 0 : 1], a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dirac1d(int N, cx<R> *psi, const void *V0, const void *const *tw, const Dirac1DArgs &a,
+                          hipStream_t st)
+{
+    switch (N) {
+    case 64: return dirac1d_n<R, 64>(psi, V0, tw, a, st);
+    case 128: return dirac1d_n<R, 128>(psi, V0, tw, a, st);
+    case 256: return dirac1d_n<R, 256>(psi, V0, tw, a, st);
+    case 512: return dirac1d_n<R, 512>(psi, V0, tw, a, st);
+    case 1024: return dirac1d_n<R, 1024>(psi, V0, tw, a, st);
+    case 2048: return dirac1d_n<R, 2048>(psi, V0, tw, a, st);
+    case 4096: return dirac1d_n<R, 4096>(psi, V0, tw, a, st);
+    case 8192: return dirac1d_n<R, 8192>(psi, V0, tw, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_dirac1d<float>(int, cx<float> *, const void *, const void *const *,
+                                          const Dirac1DArgs &, hipStream_t);
+template hipError_t launch_dirac1d<double>(int, cx<double> *, const void *, const void *const *,
+                                           const Dirac1DArgs &, hipStream_t);
+
 template hipError_t launch_dirac_xpass<float>(int, cx<float> *, int, int64_t, const void *, const void *,
                                               const DiracPhaseArgs &, int, hipStream_t);
 template hipError_t launch_dirac_xpass<double>(int, cx<double> *, int, int64_t, const void *, const void *,

@@ -203,6 +203,21 @@ template <typename R>
 hipError_t launch_dirac_colpass(int N, cx<R> *psi, int nx, int64_t plane, const void *tw,
                                 const DiracKinArgs &kin, int mode, hipStream_t st);
 
+// 1-D two-component Dirac run (one work-group per line; alpha_1 = sigma_x,
+// beta = sigma_z).  Per k, u[3 k + {0, 1, 2}] = U00, U01 (= U10), U11 of
+// exp(-i tau H(p) / hbar) / N.  Real space, half step of step s:
+// exp(-i aV_half V0) (cos a + i sin a sigma_x), a = aA * abar[s N + x]
+// (aA = q c / (2 hbar); abar null: a = 0); consecutive halves merge.
+struct Dirac1DArgs {
+    const double2 *u;
+    const double *abar;
+    int64_t step0, nsteps;
+    double aV_half, aA;
+};
+template <typename R>
+hipError_t launch_dirac1d(int N, cx<R> *psi, const void *V0, const void *const *tw, const Dirac1DArgs &a,
+                          hipStream_t st);
+
 // FP64 reductions over n complex values: sum |a|^2 -> out[0]; or sum conj(a) b -> out[0..1].
 template <typename R>
 hipError_t launch_norm(const cx<R> *a, int64_t n, double *partials, double *out, hipStream_t st);

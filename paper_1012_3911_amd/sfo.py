@@ -144,7 +144,7 @@ class Grid:
         self.desc = d
         self.n = tuple(int(x) for x in n)
         self.ndim = len(n)
-        self.ncomp = 4 if equation == "dirac" else 1
+        self.ncomp = (2 if len(n) == 1 else 4) if equation == "dirac" else 1
         self.dtype = dtype
         self.torch_dtype = torch.complex64 if dtype == "c64" else torch.complex128
         self.stream = stream if stream is not None else torch.cuda.current_stream()
