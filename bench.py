@@ -249,10 +249,21 @@ def bench_config(wl, dtype, runs=2):
 
 
 def bench_configs():
+    import numpy as np
     from paper_1012_3911_amd import workloads as W
+
+    def dirac_1d(N=4096, S=1000, dt=2e-4, L=10.0):
+        # a bound packet in a soft-core well driven by a travelling A_1(x, t), complex128
+        x = -L + 2 * L / N * np.arange(N)
+        psi0 = np.stack([np.exp(-x ** 2 / 2 + 1.5j * x), 0.004 * (1.5 - 1j * x) * np.exp(-x ** 2 / 2)])
+        t = dt * (np.arange(S) + 0.5)
+        abar = dt * 30.0 * np.sin(0.8 * x[None, :] - 40.0 * t[:, None])
+        return W.Workload("dirac1d", "dirac", (N,), (-L,), (L,), dt, S, -1.0 / np.sqrt(x ** 2 + 1.0),
+                          psi0.astype(complex), abar_y=abar)
 
     res = {}
     for name, make, dtype, runs in (("1d_harmonic 1024 c128", lambda: W.harmonic_1d(), "c128", 5),
+                                    ("1d_dirac 4096 c128", dirac_1d, "c128", 2),
                                     ("3d_wells 256^3 c64", lambda: W.wells_3d(), "c64", 2),
                                     ("2d_dirac_softcore_laser 1024^2 c128", lambda: W.dirac_softcore_laser(), "c128", 2)):
         res[name] = bench_config(make(), dtype, runs)

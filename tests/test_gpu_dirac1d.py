@@ -56,3 +56,25 @@ def test_dirac1d_steps_from_an_offset():
     ref = orc.dirac1d(wl.psi0, (512,), wl.xmin, wl.xmax, wl.dt, wl.V0, wl.abar_y, step0=30, nsteps=30, c=C)
     assert rel_l2(psi.cpu().numpy(), ref) < 1e-11
     g.close()
+
+
+def test_free_positive_energy_packet_group_velocity():
+    """The GPU run of a free positive-energy packet moves its centre of mass
+    by S tau <c^2 p / E> (complex128)."""
+    import torch
+    from test_oracle_dirac1d import _positive_energy_packet
+
+    N, L, c, dt, S = 1024, 40.0, 5.0, 0.01, 400
+    x, k, E, psi0 = _positive_energy_packet(N, L, 2.0, 0.6, c)
+    wl = W.Workload("free", "dirac", (N,), (-L,), (L,), dt, S, np.zeros(N), psi0, abar_y=None, c=c)
+    g = make_grid(wl, "c128")
+    psi = to_device(psi0, "c128")
+    g.propagate(psi, 0, S)
+    torch.cuda.synchronize()
+    out = psi.cpu().numpy()
+    rho0, rho1 = np.sum(np.abs(psi0) ** 2, axis=0), np.sum(np.abs(out) ** 2, axis=0)
+    shift = np.sum(x * rho1) / np.sum(rho1) - np.sum(x * rho0) / np.sum(rho0)
+    w = np.sum(np.abs(np.fft.fft(psi0, axis=1)) ** 2, axis=0)
+    vg = np.sum(w * c * c * k / E) / np.sum(w)
+    assert abs(shift - S * dt * vg) < 1e-9
+    g.close()

@@ -59,3 +59,33 @@ def test_norm_is_conserved():
     out = orc.dirac1d(psi0, N, -L, L, 0.003, V, abar, nsteps=200, mass=M, charge=Q, c=C)
     n0, n1 = np.sum(np.abs(psi0) ** 2), np.sum(np.abs(out) ** 2)
     assert abs(n1 / n0 - 1) < 1e-13
+
+
+def _positive_energy_packet(N, L, p0, sigma, c, m=1.0):
+    """A free packet of positive-energy states only: in momentum space each
+    component of g(p) (Gaussian around p0) along the eigenvector of
+    H(p) = c p sigma_x + m c^2 sigma_z with eigenvalue +E(p)."""
+    x = -L + 2 * L / N * np.arange(N)
+    k = 2 * np.pi * np.fft.fftfreq(N, 2 * L / N)
+    E = np.sqrt(m ** 2 * c ** 4 + c ** 2 * k ** 2)
+    g = np.exp(-((k - p0) ** 2) / (4 * sigma ** 2)) * np.exp(-1j * k * x[0])
+    v0, v1 = E + m * c * c, c * k  # unnormalised eigenvector of +E
+    nrm = np.sqrt(v0 ** 2 + v1 ** 2)
+    psi = np.stack([np.fft.ifft(g * v0 / nrm), np.fft.ifft(g * v1 / nrm)])
+    return x, k, E, psi
+
+
+def test_free_positive_energy_packet_moves_with_its_group_velocity():
+    """A free positive-energy packet has d<x>/dt = <c^2 p / E> exactly (no
+    Zitterbewegung without negative-energy components): the centre of mass
+    after S steps is <x>_0 + S tau <c^2 p/E>, the mean taken over |psi~(p)|^2."""
+    Nn, Ln, c = 1024, 40.0, 5.0
+    x, k, E, psi0 = _positive_energy_packet(Nn, Ln, 2.0, 0.6, c)
+    dt, S = 0.01, 400
+    out = orc.dirac1d(psi0, Nn, -Ln, Ln, dt, np.zeros(Nn), None, nsteps=S, c=c)
+    rho0, rho1 = np.sum(np.abs(psi0) ** 2, axis=0), np.sum(np.abs(out) ** 2, axis=0)
+    xm0, xm1 = np.sum(x * rho0) / np.sum(rho0), np.sum(x * rho1) / np.sum(rho1)
+    w = np.sum(np.abs(np.fft.fft(psi0, axis=1)) ** 2, axis=0)
+    vg = np.sum(w * c * c * k / E) / np.sum(w)
+    assert abs((xm1 - xm0) - S * dt * vg) < 1e-9
+    assert abs(xm1 - xm0) > 5.0  # it did move
