@@ -232,14 +232,14 @@ def bench_config(wl, dtype, runs=2):
     npts = wl.npoints
     s = 8 if dtype == "c64" else 16
     v = 4 if dtype == "c64" else 8
-    if wl.equation == "dirac":
+    if wl.ndim == 1:
+        step_bytes = None  # 1-D: the line stays on chip for the whole run
+    elif wl.equation == "dirac":
         step_bytes = npts * (2 * 2 * 4 * s + v)  # row + column pass over 4 components, potential
     elif wl.ndim == 3:
         step_bytes = npts * (4 * 2 * s + v)  # x, y, z, y^-1 passes, potential
-    elif wl.ndim == 2:
-        step_bytes = npts * (2 * 2 * s + v)
     else:
-        step_bytes = None  # 1-D: the line stays on chip for the whole run
+        step_bytes = npts * (2 * 2 * s + v)
     out = {"grid": list(wl.n), "dtype": dtype, "steps_per_run": wl.nsteps, "ms_per_step": 1e3 * t,
            "updates_per_s": npts / t, "plan": plan}
     if step_bytes:
