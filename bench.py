@@ -50,15 +50,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "807798215e397f8424670afb4d0e759beef7875b438f3997445abafd9dd345bb",
+    "sources_sha256": "9cf3db7d9c3439f74f458290667121570bfebffe675a5fad369807f7d76d4e84",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
     "row/0": (24724, 32768), "row/1": (24726, 32768), "row/2": (24719, 32768), "row/3": (24726, 32768),
     "row/4": (24722, 32768), "row/5": (24702, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
     "row/8": (24687, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
     "row/12": (24721, 32768), "row/13": (24702, 32768),
-    "column/0": (16663, 32843), "column/1": (16659, 32777), "column/2": (16660, 33295),
-    "column/4": (16650, 32779), "column/5": (16660, 33458), "column/7": (16771, 32798),
-    "column/8": (16629, 33989),
+    "column/0": (16663, 32858), "column/1": (16658, 32776), "column/2": (16660, 33291),
+    "column/4": (16651, 32778), "column/5": (16660, 33485), "column/7": (16771, 32796),
+    "column/8": (16628, 34042),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
 
