@@ -154,6 +154,18 @@ sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nstep
  * keeps a state-sized reference buffer on the handle.  Asynchronous. */
 sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double *chi_dev);
 
+/* Windowed eigenfunction of the eigenstate method (the eigenstate section,
+ * third equation) as the rectangle rule over t_j = j dt, T = nsteps dt:
+ * advances psi in place by nsteps steps of the time-independent potential
+ * and writes out = sum_j dt (1 - cos(2 pi j / nsteps)) exp(i E j dt / hbar)
+ * psi_j, j < nsteps (unnormalised; psi_j the state after j steps), in the
+ * state's dtype and layout.  The sum is accumulated in FP64 between the
+ * passes of each step (a state-sized complex128 buffer the library keeps on
+ * the handle) and brought to real space once at the end.  2-D and 3-D
+ * Schroedinger grids with no field table set (SFO_E_UNSUPPORTED otherwise);
+ * psi and out distinct device buffers the caller owns.  Asynchronous. */
+sfo_status sfo_eigenfunction(sfo_grid g, void *psi_dev, int64_t nsteps, double energy, void *out_dev);
+
 /* Windowed Fourier transform of an autocorrelation (the eigenstate section,
  * second equation) as the rectangle rule over t_j = j dt, T = nsteps dt:
  * out[2e], out[2e+1] = re, im of sum_j dt chi_j (1 - cos(2 pi j / nsteps))

@@ -127,11 +127,12 @@ __device__ __forceinline__ void block_part3(double (&v)[3], double (*red)[3], do
 // M_GRAD (NS = 2) additionally forms b = Im(conj(g) psi) at this step
 // boundary in real space: acc += w b (the dL/dV0 accumulator) and the
 // moments sum_x (x b, y b, z b), summed over the work-group into ga.part.
+//
 // Row tile addressing: the base of element m of the tile's first row is
-// uniform and is kept in scalar registers (an opaque copy stops the compiler
-// from folding it into a 64-bit vector address); a thread adds its own
-// 32-bit offset (line * N + t) * size.  Only for values uniform over the
-// work-group.
+// uniform and is kept in scalar registers (scalar_base: an opaque copy stops
+// the compiler from folding it into a 64-bit vector address); a thread adds
+// its own 32-bit offset (line * N + t) * size.  scalar_base is only for
+// values uniform over the work-group.
 template <typename P> __device__ __forceinline__ P scalar_base(P p)
 {
     __asm__ __volatile__("" : "+s"(p));

@@ -81,6 +81,7 @@ struct sfo_grid_s {
     void *chi_ref = nullptr;  // autocorrelation: reference state in k-space
     size_t chi_ref_bytes = 0;
     double2 *du = nullptr;  // 1-D Dirac: U00, U01, U11 of the momentum-space step per k
+    double2 *eig_acc = nullptr;  // windowed eigenfunction: FP64 accumulator (ntot)
     // velocity gauge: per-step, per-axis kinetic factors (vsteps x n[a] each)
     double2 *vtab[3] = {nullptr, nullptr, nullptr};
     int64_t vsteps = 0;
@@ -127,6 +128,7 @@ void free_grid(sfo_grid g)
     (void)hipFree(g->chi_ref);
     for (int a = 0; a < 3; ++a) (void)hipFree(g->vtab[a]);
     (void)hipFree(g->du);
+    (void)hipFree(g->eig_acc);
     delete g;
 }
 
@@ -528,6 +530,43 @@ template <typename R> sfo_status schro_autocorr(sfo_grid g, void *psi, int64_t n
     }
     HIP_TRY(launch_chi_sum(g->part, nslots, nsteps, g->dv / (double)g->ntot, chi, g->st));
     return SFO_OK;
+}
+
+// Windowed eigenfunction (the eigenstate method): Psi_E = sum_j tau w_j
+// exp(i E j tau / hbar) psi_j, j < nsteps, w_j = 1 - cos(2 pi j / nsteps),
+// while psi advances nsteps steps.  Between the column pass of step j - 1
+// and the row pass of step j the buffer holds F_x P^-1 psi_j (P the half
+// factor, the same for every step with a time-independent potential), and
+// F_x P^-1 is linear and fixed, so the weighted sum of those buffers is
+// F_x P^-1 Psi_E: it is accumulated in FP64 there (w_0 = 0, so step 0 adds
+// nothing), and one inverse x-transform with the half factor at the end
+// gives Psi_E.
+template <typename R> sfo_status schro_eigen(sfo_grid g, void *psi, int64_t nsteps, double E, void *out)
+{
+    const int64_t n = g->ntot;
+    if (!g->eig_acc) HIP_TRY(hipMalloc(&g->eig_acc, sizeof(double2) * (size_t)n));
+    HIP_TRY(hipMemsetAsync(g->eig_acc, 0, sizeof(double2) * (size_t)n, g->st));
+    const double tau = g->d.dt, hb = g->d.hbar;
+    sfo_status s;
+    if (nsteps > 0) {
+        if ((s = schro_xpass<R>(g, psi, nullptr, -1, 0, +1, M_PHASE | M_FWD))) return s;
+        for (int64_t j = 0; j < nsteps; ++j) {
+            if ((s = schro_colpasses<R>(g, psi, nullptr, M_FWD | M_KIN | M_INV, +1))) return s;
+            const int64_t b = j + 1;  // the step boundary now in the buffer
+            if (b < nsteps) {
+                const double w = tau * (1.0 - std::cos(2.0 * M_PI * (double)b / (double)nsteps));
+                const double ph = E * tau * (double)b / hb;
+                HIP_TRY(launch_eig_axpy<R>((const cx<R> *)psi, g->eig_acc, n, w * std::cos(ph), w * std::sin(ph),
+                                           g->st));
+            }
+            const bool more = j + 1 < nsteps;
+            if ((s = schro_xpass<R>(g, psi, nullptr, 0, more ? 0 : -1, +1, M_INV | M_PHASE | (more ? M_FWD : 0))))
+                return s;
+        }
+    }
+    // Psi_E = P F_x^-1 acc, in the state's precision
+    HIP_TRY(launch_acc_to_state<R>(g->eig_acc, (cx<R> *)out, n, g->st));
+    return schro_xpass<R>(g, out, nullptr, -1, 0, +1, M_INV | M_PHASE);
 }
 
 // ------------------------------------------------------------- planning --
@@ -1491,6 +1530,19 @@ sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double
         return fail(SFO_E_UNSUPPORTED, "the autocorrelation run needs a time-independent potential: clear the field table");
     return g->c128 ? schro_autocorr<double>(g, psi_dev, nsteps, chi_dev)
                    : schro_autocorr<float>(g, psi_dev, nsteps, chi_dev);
+}
+
+sfo_status sfo_eigenfunction(sfo_grid g, void *psi_dev, int64_t nsteps, double energy, void *out_dev)
+{
+    if (!g || !psi_dev || !out_dev) return fail(SFO_E_INVALID, "null grid, state or output");
+    if (psi_dev == out_dev) return fail(SFO_E_INVALID, "psi and the output must be distinct buffers");
+    if (nsteps < 0 || !std::isfinite(energy)) return fail(SFO_E_INVALID, "need nsteps >= 0 and a finite energy");
+    if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
+        return fail(SFO_E_UNSUPPORTED, "the eigenfunction run is built for 2-D and 3-D Schroedinger grids");
+    if (g->ebar_steps > 0 || g->vsteps > 0)
+        return fail(SFO_E_UNSUPPORTED, "the eigenfunction run needs a time-independent potential: clear the field table");
+    return g->c128 ? schro_eigen<double>(g, psi_dev, nsteps, energy, out_dev)
+                   : schro_eigen<float>(g, psi_dev, nsteps, energy, out_dev);
 }
 
 sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const double *energies_dev, int32_t nE,

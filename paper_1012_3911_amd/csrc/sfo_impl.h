@@ -179,6 +179,11 @@ hipError_t launch_chi_sum(const double *part, int nslots, int64_t nsteps, double
 hipError_t launch_spectrum(const double *chi, int64_t nsteps, double dt, double hbar, const double *E, int nE,
                            double *out, hipStream_t st);
 
+// acc[i] += (cr + i ci) s[i] (FP64 accumulator); out[i] = acc[i] rounded to R.
+template <typename R>
+hipError_t launch_eig_axpy(const cx<R> *s, double2 *acc, int64_t n, double cr, double ci, hipStream_t st);
+template <typename R> hipError_t launch_acc_to_state(const double2 *acc, cx<R> *out, int64_t n, hipStream_t st);
+
 // Number of work-groups (= gradient partial slots) of a row pass launch.
 template <typename R> int xpass_groups(int variant, int N, int64_t nrows);
 

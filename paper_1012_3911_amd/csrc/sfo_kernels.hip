@@ -216,6 +216,26 @@ __global__ void k_convert_v0(const double *__restrict__ src, void *dst, int to_f
     }
 }
 
+// Windowed eigenfunction: acc += (cr + i ci) s in FP64, and the final
+// rounding of the accumulator to the state's precision.
+template <typename R>
+__global__ void k_eig_axpy(const cx<R> *__restrict__ s, double2 *__restrict__ acc, int64_t n, double cr, double ci)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)s[i].re, b = (double)s[i].im;
+        double2 r = acc[i];
+        r.x += cr * a - ci * b;
+        r.y += cr * b + ci * a;
+        acc[i] = r;
+    }
+}
+
+template <typename R> __global__ void k_acc_to_state(const double2 *__restrict__ acc, cx<R> *__restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = {(R)acc[i].x, (R)acc[i].y};
+}
+
 // ------------------------------------------------------------ host helpers --
 void line_stages(int N, int RAD, int *radix, int *span, int *nst)
 {
@@ -337,6 +357,24 @@ hipError_t launch_absmax(const double *src, int64_t n, double *partials, double 
     hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, st, (const double *)partials, kReduceBlocks, out);
     return hipGetLastError();
 }
+
+template <typename R>
+hipError_t launch_eig_axpy(const cx<R> *s, double2 *acc, int64_t n, double cr, double ci, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_eig_axpy<R>, dim3(2048), dim3(256), 0, st, s, acc, n, cr, ci);
+    return hipGetLastError();
+}
+
+template <typename R> hipError_t launch_acc_to_state(const double2 *acc, cx<R> *out, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_acc_to_state<R>, dim3(2048), dim3(256), 0, st, acc, out, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_eig_axpy<float>(const cx<float> *, double2 *, int64_t, double, double, hipStream_t);
+template hipError_t launch_eig_axpy<double>(const cx<double> *, double2 *, int64_t, double, double, hipStream_t);
+template hipError_t launch_acc_to_state<float>(const double2 *, cx<float> *, int64_t, hipStream_t);
+template hipError_t launch_acc_to_state<double>(const double2 *, cx<double> *, int64_t, hipStream_t);
 
 hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t n, hipStream_t st)
 {

@@ -55,7 +55,7 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
            "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
-           "sfo_spectrum", "sfo_set_vector_field", "sfo_last_error", "sfo_version"]
+           "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_last_error", "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 TIME_IN_STEP = 16  # or'ed into a kernel kind: time the pass within whole steps
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "sfo_autocorrelation": [P, P, I64, P],
         "sfo_spectrum": [P, P, I64, P, I32, P],
         "sfo_set_vector_field": [P, P, P, I64],
+        "sfo_eigenfunction": [P, P, I64, ctypes.c_double, P],
         "sfo_create_batch": [P, I32, P, ctypes.POINTER(P)],
         "sfo_destroy_batch": [P],
         "sfo_propagate_batch": [P, P, I64, I64],
@@ -231,6 +232,15 @@ class Grid:
         _check(_lib.sfo_autocorrelation(self._h, self._state(psi), int(nsteps),
                                         ctypes.c_void_p(chi.data_ptr())), "sfo_autocorrelation")
         return torch.view_as_complex(chi.view(-1, 2))
+
+    def eigenfunction(self, psi, nsteps: int, energy: float):
+        """Advance psi by nsteps steps (no field) and return the windowed sum
+        sum_j dt w_j exp(i E j dt / hbar) psi_j (unnormalised) as a new state tensor."""
+        torch = _torch()
+        out = torch.empty_like(psi)
+        _check(_lib.sfo_eigenfunction(self._h, self._state(psi), int(nsteps), float(energy), self._state(out, "out")),
+               "sfo_eigenfunction")
+        return out
 
     def spectrum(self, chi, energies):
         """Windowed transform of an autocorrelation at the given energies (complex128 CUDA tensor)."""

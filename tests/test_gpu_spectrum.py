@@ -97,3 +97,28 @@ def test_autocorrelation_rejects():
     with pytest.raises(sfo.SfoError):
         g1.autocorrelation(to_device(w1.psi0, "c128"), 4)
     g1.close()
+
+
+@pytest.mark.parametrize("dtype,n,tol", [("c128", (128, 64), 1e-10), ("c64", (128, 64), 2e-5),
+                                         ("c128", (64, 64, 64), 1e-10)])
+def test_eigenfunction_matches_oracle(dtype, n, tol):
+    """The windowed eigenfunction sum (eigenstate section, third equation) on
+    the GPU against the oracle's sum over its own steps, both normalised; the
+    state after the run against the oracle's."""
+    import torch
+
+    S = 160 if len(n) == 2 else 24
+    wl = _wl(n, 12.0, 0.05, S)
+    g = make_grid(wl, dtype)
+    psi = to_device(wl.psi0, dtype)
+    E = -0.45
+    out = g.eigenfunction(psi, S, E)
+    torch.cuda.synchronize()
+    p0 = wl.psi0.astype(np.complex64).astype(complex) if dtype == "c64" else wl.psi0
+    ref = orc.eigenfunction(p0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, S, E)
+    o = out.cpu().numpy().astype(complex)
+    o /= np.sqrt(orc.norm(o, wl.n, wl.xmin, wl.xmax))
+    assert rel_l2(o, ref) < tol
+    _, psi_ref = orc.autocorrelation(p0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, S)
+    assert rel_l2(psi.cpu().numpy(), psi_ref) < (1e-12 if dtype == "c128" else 1e-5)
+    g.close()
