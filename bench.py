@@ -50,15 +50,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "9cf3db7d9c3439f74f458290667121570bfebffe675a5fad369807f7d76d4e84",
+    "sources_sha256": "ea3ade385d665e590b417e4c5b8556b42414e1e817cefa9ced1ae200f88da2b6",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
     "row/0": (24724, 32768), "row/1": (24726, 32768), "row/2": (24719, 32768), "row/3": (24726, 32768),
-    "row/4": (24722, 32768), "row/5": (24702, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
+    "row/4": (24722, 32768), "row/5": (24703, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
     "row/8": (24687, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
     "row/12": (24721, 32768), "row/13": (24702, 32768),
-    "column/0": (16663, 32858), "column/1": (16658, 32776), "column/2": (16660, 33291),
-    "column/4": (16651, 32778), "column/5": (16660, 33485), "column/7": (16771, 32796),
-    "column/8": (16628, 34042),
+    "column/0": (16663, 32831), "column/1": (16659, 32777), "column/2": (16660, 33253),
+    "column/4": (16650, 32778), "column/5": (16660, 33420), "column/7": (16767, 32830),
+    "column/8": (16631, 36339),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
 
