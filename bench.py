@@ -14,7 +14,9 @@ the complex64 path (FP32 storage and butterflies, FP64 phases and
 reductions); the complex128 path, fused and in the paper's unfused
 five-launch form, is reported beside it, and so are the forward run plus
 reverse sweep (adjoint) of the same workload and the 64-problem batched
-control workload (forward, and forward + reverse sweep).
+control workload (forward, and forward + reverse sweep).  As an external
+point of comparison only, the same steps written with torch.fft (the vendor
+hipFFT/rocFFT) and torch elementwise products are timed too.
 
 Roofline: the dominant pass's algorithmic bytes per launch divided by its
 average launch duration within steps of the propagation's pass sequence,
@@ -390,6 +392,75 @@ def bench_beyond_mall(steps=40):
                             "frac": alg[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS} for k, v in kern.items()}}
 
 
+def bench_library_fft(wl, steps=500, warmup=50, check_steps=20):
+    """An external point of comparison, not the product path: the same
+    Strang steps written with the vendor FFT library behind torch.fft
+    (hipFFT/rocFFT) and torch elementwise products, adjacent potential halves
+    merged, factors precomputed once.  Each step is a forward and an inverse
+    2-D transform, the kinetic product and the merged potential product.
+    After `check_steps` steps from psi0 its complex128 result is compared with
+    the sfo complex128 path, to show that both compute the same steps."""
+    import numpy as np
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    Ny, Nx = wl.n
+    dx = [(wl.xmax[a] - wl.xmin[a]) / wl.n[a] for a in range(2)]
+    x = wl.xmin[0] + dx[0] * np.arange(Nx)
+    kx = 2 * np.pi * np.fft.fftfreq(Nx, d=dx[0])
+    ky = 2 * np.pi * np.fft.fftfreq(Ny, d=dx[1])
+    half_v = np.exp(-0.5j * wl.dt * wl.V0)
+    kin = np.exp(-0.5j * wl.dt * (ky[:, None] ** 2 + kx[None, :] ** 2))
+    half_x = np.exp(-0.5j * np.outer(wl.ebar[:, 0], x))  # (nsteps, Nx)
+    nxt = np.roll(np.arange(wl.nsteps), -1)
+    out = {"what": "torch.fft (hipFFT/rocFFT) split step, merged halves", "grid": [Ny, Nx]}
+    for dtype, tdt in (("c64", torch.complex64), ("c128", torch.complex128)):
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(tdt)
+        V1, V2, K = dev(half_v), dev(half_v * half_v), dev(kin)
+        X1, X2 = dev(half_x), dev(half_x * half_x[nxt])
+        psi = dev(wl.psi0)
+        buf = torch.empty_like(psi)
+
+        def run(psi, n0, count):
+            # opening half of step n0, then per step: transforms, kinetic factor,
+            # closing half merged with the next step's opening half
+            psi.mul_(V1).mul_(X1[n0 % wl.nsteps])
+            for j in range(count):
+                n = (n0 + j) % wl.nsteps
+                torch.fft.fft2(psi, out=buf)
+                buf.mul_(K)
+                torch.fft.ifft2(buf, out=psi)
+                if j + 1 < count:
+                    psi.mul_(V2).mul_(X2[n])
+                else:
+                    psi.mul_(V1).mul_(X1[n])
+            return psi
+
+        run(psi, 0, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(psi, 0, steps)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        out[dtype] = {"ms_per_step": 1e3 * t, "updates_per_s": Ny * Nx / t}
+        if dtype == "c128":
+            psi.copy_(dev(wl.psi0))
+            run(psi, 0, check_steps)
+            g = sfo.Grid(wl.n, wl.xmin, wl.xmax, wl.dt, dtype="c128")
+            g.set_potential(wl.V0)
+            g.set_field(wl.ebar)
+            ours = dev(wl.psi0)
+            g.propagate(ours, 0, check_steps)
+            torch.cuda.synchronize()
+            out["c128_rel_l2_vs_sfo_after_%d_steps" % check_steps] = float(
+                torch.linalg.vector_norm(psi - ours) / torch.linalg.vector_norm(ours))
+            g.close()
+            del ours
+        del V1, V2, K, X1, X2, psi, buf
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size: the HBM counters of this kernel
     calibrate FETCH_SIZE / WRITE_SIZE of the split-step kernels."""
@@ -546,6 +617,11 @@ def main():
         out["autocorrelation"] = bench_autocorrelation()
         print("# autocorrelation 2048^2 c64 %.4f ms/step (plain run %.4f)" % (
             out["autocorrelation"]["ms_per_step"], out["autocorrelation"]["ms_per_step_without_chi"]),
+            file=sys.stderr, flush=True)
+        lib = bench_library_fft(wl)
+        out["library_fft_comparison"] = lib
+        print("# torch.fft split step: c64 %.4f ms/step, c128 %.4f ms/step; c128 rel L2 vs sfo %.2e" % (
+            lib["c64"]["ms_per_step"], lib["c128"]["ms_per_step"], lib["c128_rel_l2_vs_sfo_after_20_steps"]),
             file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
