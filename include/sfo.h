@@ -104,14 +104,19 @@ sfo_status sfo_destroy_grid(sfo_grid g);
  * complex64 states and in FP64 for complex128 states (the phase argument is
  * always formed in FP64).  Synchronises the stream (it also records max|V0|,
  * which selects the shorter sin/cos series when every potential phase of a
- * step is below 1/8 rad).  Errors: SFO_E_INVALID for a non-finite value. */
+ * step is below 1/8 rad).  Errors: SFO_E_INVALID for a non-finite value,
+ * checked before anything is copied (the previous potential stays). */
 sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev);
 
 /* Copy the per-step field integrals Ebar[step][axis] (host, FP64,
  * nsteps x ndim, axis x first) into a device table indexed by absolute step
  * number.  Steps beyond the table are an error at propagation time; with no
  * table the field is zero.  Also releases velocity-gauge tables
- * (sfo_set_vector_field).  Schroedinger only. */
+ * (sfo_set_vector_field).  Schroedinger only.  At most 2^28 steps
+ * (SFO_E_UNSUPPORTED beyond).  Errors leave the previous table in place:
+ * SFO_E_INVALID for a non-finite value, SFO_E_NOMEM when the host or device
+ * copy cannot be allocated.  Synchronises the stream before the old table is
+ * released. */
 sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
 
 /* Velocity gauge of the dipole approximation (the split's momentum-space
@@ -120,16 +125,21 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
  * step integrals int A_a dt' (x first); a2bar_host: nsteps step integrals of
  * |A|^2; FP64 host arrays, copied: the library builds per-step, per-axis
  * kinetic tables (nsteps x (n[0] + n[1] + n[2]) complex FP64 on the device,
- * at most 1 GiB: SFO_E_UNSUPPORTED beyond).  Replaces a length-gauge field
- * table; sfo_set_field (any nsteps) in turn releases these tables.  nsteps
- * = 0 clears.  2-D and 3-D Schroedinger grids (1-D: SFO_E_UNSUPPORTED);
+ * at most 1 GiB and 2^28 steps: SFO_E_UNSUPPORTED beyond).  Replaces a
+ * length-gauge field table; sfo_set_field (any nsteps) in turn releases these
+ * tables.  nsteps = 0 clears.  Arguments are checked (SFO_E_INVALID for a
+ * non-finite value) before anything changes; a failed allocation
+ * (SFO_E_NOMEM) leaves the grid with no field at all.  2-D and 3-D Schroedinger grids (1-D: SFO_E_UNSUPPORTED);
  * sfo_step / sfo_propagate use it; sfo_adjoint, sfo_autocorrelation and
  * batches refuse a grid that has it (SFO_E_UNSUPPORTED). */
 sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps);
 
 /* Copy the per-step vector-potential integrals Abar_y[step][ix] (host,
  * FP64, nsteps x n[0]) of a field A = A_y(x, t) y_hat (2-D; in 1-D the
- * line's own component A_1(x, t)).  Dirac only. */
+ * line's own component A_1(x, t)).  Dirac only.  At most 1 GiB of table
+ * (SFO_E_UNSUPPORTED beyond).  Errors leave the previous table in place:
+ * SFO_E_INVALID for a non-finite value, SFO_E_NOMEM when a copy cannot be
+ * allocated.  Synchronises the stream before the old table is released. */
 sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps);
 
 /* One un-merged Strang step number `step_index` applied in place to psi. */

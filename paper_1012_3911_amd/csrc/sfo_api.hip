@@ -9,6 +9,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -44,6 +45,38 @@ sfo_status fail(sfo_status s, const char *fmt, ...)
     } while (0)
 
 bool is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+// Longest field or vector-potential table a grid accepts, in steps.
+constexpr int64_t kMaxTableSteps = int64_t(1) << 28;
+
+// No C++ exception crosses the C ABI: a host allocation sized by the caller
+// that fails reports SFO_E_NOMEM.
+template <typename F> sfo_status no_throw(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(SFO_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(SFO_E_INVALID, "%s", ex.what());
+    }
+}
+
+// Device copy of a host table; on failure nothing stays allocated.
+sfo_status upload_table(const double *host, size_t count, double **out)
+{
+    *out = nullptr;
+    if (count == 0) return SFO_OK;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * count));
+    const hipError_t e = hipMemcpy(d, host, sizeof(double) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(SFO_E_HIP, "table upload: %s", hipGetErrorString(e));
+    }
+    *out = d;
+    return SFO_OK;
+}
 
 }  // namespace
 
@@ -1148,6 +1181,26 @@ void free_batch(sfo_batch b)
     delete b;
 }
 
+// The grids of a batch grouped by shape, in order of first appearance.
+void group_batch(sfo_batch b, const sfo_grid *grids, int count)
+{
+    b->grids.assign(grids, grids + count);
+    for (int i = 0; i < count; ++i) {
+        const sfo_grid g = grids[i];
+        bool found = false;
+        for (const auto &G : b->groups)
+            found |= G.ndim == g->ndim && G.nx == (int)g->n[0] && G.ny == (int)g->n[1];
+        if (found) continue;
+        sfo_batch_s::Group G{g->ndim, (int)g->n[0], (int)g->n[1], (int)b->ids.size(), 0, g};
+        for (int k = i; k < count; ++k)
+            if (grids[k]->ndim == G.ndim && (int)grids[k]->n[0] == G.nx && (int)grids[k]->n[1] == G.ny) {
+                b->ids.push_back(k);
+                ++G.count;
+            }
+        b->groups.push_back(G);
+    }
+}
+
 // Descriptors of every problem for one call; *work_need: the moment and
 // partial workspace of a reverse sweep (doubles).
 template <typename R>
@@ -1384,7 +1437,8 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     if (e == hipSuccess) e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return fail(SFO_E_HIP, "no HIP device: %s", hipGetErrorString(e));
 
-    sfo_grid g = new sfo_grid_s;
+    sfo_grid g = new (std::nothrow) sfo_grid_s;
+    if (!g) return fail(SFO_E_NOMEM, "host allocation failed");
     g->d = d;
     g->st = (hipStream_t)hip_stream;
     g->ndim = d.ndim;
@@ -1403,9 +1457,9 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
         default_plan<float>(g);
     sfo_status s = SFO_OK;
     auto guard = [&](sfo_status r) { if (r != SFO_OK) { free_grid(g); } return r; };
-    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_twiddles(g, a);
-    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = make_kinetic(g, a);
-    if (s == SFO_OK && d.equation == SFO_DIRAC && d.ndim == 1) s = make_dirac1d_kinetic(g);
+    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = no_throw([&] { return make_twiddles(g, a); });
+    for (int a = 0; a < d.ndim && s == SFO_OK; ++a) s = no_throw([&] { return make_kinetic(g, a); });
+    if (s == SFO_OK && d.equation == SFO_DIRAC && d.ndim == 1) s = no_throw([&] { return make_dirac1d_kinetic(g); });
     if (s != SFO_OK) return guard(s);
     const double2 one = {1.0, 0.0};
     hipError_t he = hipMalloc(&g->one, sizeof(double2));
@@ -1431,13 +1485,14 @@ sfo_status sfo_destroy_grid(sfo_grid g)
 sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev)
 {
     if (!g || !V0_dev) return fail(SFO_E_INVALID, "null grid or potential");
-    HIP_TRY(launch_convert_v0(V0_dev, g->V0, g->c128, g->ntot, g->st));
+    // checked before it replaces the handle's potential
     double *res = g->red + 2 * kReduceBlocks;
     HIP_TRY(launch_absmax(V0_dev, g->ntot, g->red, res, g->st));
     double m = 0.0;
     HIP_TRY(hipMemcpyAsync(&m, res, sizeof(double), hipMemcpyDeviceToHost, g->st));
     HIP_TRY(hipStreamSynchronize(g->st));
     if (!std::isfinite(m)) return fail(SFO_E_INVALID, "potential holds a non-finite value");
+    HIP_TRY(launch_convert_v0(V0_dev, g->V0, g->c128, g->ntot, g->st));
     g->v0max = m;
     return SFO_OK;
 }
@@ -1447,20 +1502,30 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "field table is for the Schroedinger equation");
     if (nsteps < 0 || (nsteps > 0 && !ebar_host)) return fail(SFO_E_INVALID, "bad field table");
-    HIP_TRY(hipStreamSynchronize(g->st));
-    release_vector_tables(g);
-    (void)hipFree(g->ebar_d);
-    g->ebar_d = nullptr;
-    g->ebar.assign(ebar_host, ebar_host + nsteps * g->ndim);
-    g->ebar_steps = nsteps;
-    if (nsteps > 0) {
-        for (double v : g->ebar)
-            if (!std::isfinite(v)) return fail(SFO_E_INVALID, "field table holds a non-finite value");
-        const size_t bytes = sizeof(double) * (size_t)nsteps * g->ndim;
-        HIP_TRY(hipMalloc(&g->ebar_d, bytes));
-        HIP_TRY(hipMemcpy(g->ebar_d, g->ebar.data(), bytes, hipMemcpyHostToDevice));
-    }
-    return SFO_OK;
+    if (nsteps > kMaxTableSteps)
+        return fail(SFO_E_UNSUPPORTED, "field tables hold at most %lld steps", (long long)kMaxTableSteps);
+    const size_t count = (size_t)nsteps * g->ndim;
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(ebar_host[i])) return fail(SFO_E_INVALID, "field table holds a non-finite value");
+    return no_throw([&]() -> sfo_status {
+        std::vector<double> host(ebar_host, ebar_host + count);
+        double *dev = nullptr;
+        sfo_status s = upload_table(host.data(), count, &dev);
+        if (s) return s;
+        const hipError_t e = hipStreamSynchronize(g->st);
+        if (e != hipSuccess) {
+            (void)hipFree(dev);
+            return fail(SFO_E_HIP, "stream: %s", hipGetErrorString(e));
+        }
+        // the new table replaces the old one (and any velocity-gauge tables)
+        // only once it is complete
+        release_vector_tables(g);
+        (void)hipFree(g->ebar_d);
+        g->ebar_d = dev;
+        g->ebar.swap(host);
+        g->ebar_steps = nsteps;
+        return SFO_OK;
+    });
 }
 
 sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps)
@@ -1472,7 +1537,7 @@ sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const doubl
         return fail(SFO_E_UNSUPPORTED, "the velocity gauge is built for 2-D and 3-D grids");
     int64_t per = 0;
     for (int a = 0; a < g->ndim; ++a) per += g->n[a];
-    if (nsteps > 0 && (double)nsteps * (double)per * sizeof(double2) > (double)(1ll << 30))
+    if (nsteps > kMaxTableSteps || (double)nsteps * (double)per * sizeof(double2) > (double)(1ll << 30))
         return fail(SFO_E_UNSUPPORTED, "vector-field tables of %lld steps exceed 1 GiB", (long long)nsteps);
     for (int64_t i = 0; i < nsteps * g->ndim; ++i)
         if (!std::isfinite(abar_host[i])) return fail(SFO_E_INVALID, "vector-field table holds a non-finite value");
@@ -1486,7 +1551,8 @@ sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const doubl
     g->ebar.clear();
     g->ebar_steps = 0;
     if (nsteps == 0) return SFO_OK;
-    sfo_status s = make_vector_tables(g, abar_host, a2bar_host, nsteps);
+    // on failure the grid is left with no field at all
+    sfo_status s = no_throw([&] { return make_vector_tables(g, abar_host, a2bar_host, nsteps); });
     if (s) release_vector_tables(g);
     return s;
 }
@@ -1496,16 +1562,28 @@ sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (g->d.equation != SFO_DIRAC) return fail(SFO_E_INVALID, "vector potential is for the Dirac equation");
     if (nsteps < 0 || (nsteps > 0 && !abar_y_host)) return fail(SFO_E_INVALID, "bad vector-potential table");
-    HIP_TRY(hipStreamSynchronize(g->st));
-    (void)hipFree(g->abar_d);
-    g->abar_d = nullptr;
-    g->abar.assign(abar_y_host, abar_y_host + nsteps * g->n[0]);
-    g->abar_steps = nsteps;
-    if (nsteps > 0) {
-        HIP_TRY(hipMalloc(&g->abar_d, sizeof(double) * nsteps * g->n[0]));
-        HIP_TRY(hipMemcpy(g->abar_d, g->abar.data(), sizeof(double) * nsteps * g->n[0], hipMemcpyHostToDevice));
-    }
-    return SFO_OK;
+    if (nsteps > kMaxTableSteps || (double)nsteps * (double)g->n[0] * sizeof(double) > (double)(1ll << 30))
+        return fail(SFO_E_UNSUPPORTED, "vector-potential tables of %lld steps exceed 1 GiB", (long long)nsteps);
+    const size_t count = (size_t)nsteps * g->n[0];
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(abar_y_host[i])) return fail(SFO_E_INVALID, "vector-potential table holds a non-finite value");
+    return no_throw([&]() -> sfo_status {
+        std::vector<double> host(abar_y_host, abar_y_host + count);
+        double *dev = nullptr;
+        sfo_status s = upload_table(host.data(), count, &dev);
+        if (s) return s;
+        const hipError_t e = hipStreamSynchronize(g->st);
+        if (e != hipSuccess) {
+            (void)hipFree(dev);
+            return fail(SFO_E_HIP, "stream: %s", hipGetErrorString(e));
+        }
+        // the new table replaces the old one only once it is complete
+        (void)hipFree(g->abar_d);
+        g->abar_d = dev;
+        g->abar.swap(host);
+        g->abar_steps = nsteps;
+        return SFO_OK;
+    });
 }
 
 sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nsteps)
@@ -1628,7 +1706,7 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps)
         }
     }
     HIP_TRY(hipStreamSynchronize(g->st));
-    sfo_status s = g->c128 ? autotune_impl<double>(g, reps) : autotune_impl<float>(g, reps);
+    sfo_status s = no_throw([&] { return g->c128 ? autotune_impl<double>(g, reps) : autotune_impl<float>(g, reps); });
     if (s) return s;
     std::lock_guard<std::mutex> lk(g_plan_mu);
     store_plan(key, {g->row_var, g->col_var[1], g->col_var[2]});
@@ -1711,25 +1789,18 @@ sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stre
         if (g->ndim > 2) return fail(SFO_E_UNSUPPORTED, "grid %d: batches hold 1-D and 2-D grids", i);
         if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "grid %d: batches run in the length gauge", i);
     }
-    sfo_batch b = new sfo_batch_s;
-    b->grids.assign(grids, grids + count);
+    sfo_batch b = new (std::nothrow) sfo_batch_s;
+    if (!b) return fail(SFO_E_NOMEM, "host allocation failed");
+    sfo_status s = no_throw([&]() -> sfo_status {
+        group_batch(b, grids, count);
+        return SFO_OK;
+    });
+    if (s) {
+        free_batch(b);
+        return s;
+    }
     b->c128 = c128;
     b->st = (hipStream_t)hip_stream;
-    // group by shape, in order of first appearance
-    for (int i = 0; i < count; ++i) {
-        const sfo_grid g = grids[i];
-        bool found = false;
-        for (const auto &G : b->groups)
-            found |= G.ndim == g->ndim && G.nx == (int)g->n[0] && G.ny == (int)g->n[1];
-        if (found) continue;
-        sfo_batch_s::Group G{g->ndim, (int)g->n[0], (int)g->n[1], (int)b->ids.size(), 0, g};
-        for (int k = i; k < count; ++k)
-            if (grids[k]->ndim == G.ndim && (int)grids[k]->n[0] == G.nx && (int)grids[k]->n[1] == G.ny) {
-                b->ids.push_back(k);
-                ++G.count;
-            }
-        b->groups.push_back(G);
-    }
     auto guard = [&](hipError_t e) {
         free_batch(b);
         return fail(e == hipErrorOutOfMemory ? SFO_E_NOMEM : SFO_E_HIP, "batch set-up: %s", hipGetErrorString(e));
@@ -1765,16 +1836,20 @@ sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on)
 sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0, int64_t nsteps)
 {
     if (!b || !psi_devs) return fail(SFO_E_INVALID, "null batch or state list");
-    return b->c128 ? batch_run<double>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr)
-                   : batch_run<float>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr);
+    return no_throw([&] {
+        return b->c128 ? batch_run<double>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr)
+                       : batch_run<float>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr);
+    });
 }
 
 sfo_status sfo_adjoint_batch(sfo_batch b, void *const *psi_devs, void *const *g_devs, int64_t step0, int64_t nsteps,
                              double *const *dL_debar_devs, double *const *dL_dV0_devs)
 {
     if (!b || !psi_devs || !g_devs) return fail(SFO_E_INVALID, "null batch, state list or adjoint list");
-    return b->c128 ? batch_run<double>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs)
-                   : batch_run<float>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs);
+    return no_throw([&] {
+        return b->c128 ? batch_run<double>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs)
+                       : batch_run<float>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs);
+    });
 }
 
 sfo_status sfo_batch_check(sfo_batch b)

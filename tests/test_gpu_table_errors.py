@@ -1,0 +1,88 @@
+"""A rejected potential or field table leaves the grid as it was.
+
+Each setter checks its argument before it replaces anything the handle
+holds, so after an SFO_E_INVALID (a non-finite value) or SFO_E_UNSUPPORTED
+(a table longer than the grid accepts) the next run gives bit for bit what
+it gave before the failed call.  Called through the C ABI on the GPU.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1012_3911_amd import workloads as W
+from gpu_util import make_grid, to_device
+
+pytestmark = pytest.mark.gpu
+
+E_INVALID, E_UNSUPPORTED = -1, -2
+MAX_TABLE_STEPS = 1 << 28
+
+
+def _run(g, wl, dtype, nsteps):
+    import torch
+
+    psi = to_device(wl.psi0, dtype)
+    g.propagate(psi, 0, nsteps)
+    torch.cuda.synchronize()
+    return psi.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_rejected_field_and_potential_keep_the_previous_ones(dtype):
+    from paper_1012_3911_amd import sfo
+
+    wl = W.softcore_2d_laser(n=64, nsteps=12, dt=0.05, L=20.0, E0=0.5)
+    g = make_grid(wl, dtype)
+    before = _run(g, wl, dtype, wl.nsteps)
+
+    bad = wl.ebar.copy()
+    bad[5, 0] = np.nan
+    with pytest.raises(sfo.SfoError) as err:
+        g.set_field(bad)
+    assert err.value.status == E_INVALID
+    # longer than any table a grid accepts: refused before the host array is read
+    rc = sfo._lib.sfo_set_field(g._h, wl.ebar.ctypes.data_as(ctypes.c_void_p), MAX_TABLE_STEPS + 1)
+    assert rc == E_UNSUPPORTED
+    badv = wl.V0.copy()
+    badv[3, 7] = np.inf
+    with pytest.raises(sfo.SfoError) as err:
+        g.set_potential(badv)
+    assert err.value.status == E_INVALID
+
+    after = _run(g, wl, dtype, wl.nsteps)
+    assert np.array_equal(after, before)
+    # a valid table still replaces the old one
+    g.set_field(2.0 * wl.ebar)
+    assert not np.array_equal(_run(g, wl, dtype, wl.nsteps), before)
+    g.close()
+
+
+def test_rejected_vector_tables_keep_the_previous_ones():
+    from paper_1012_3911_amd import sfo
+
+    wl = W.dirac_softcore_laser(n=64, nsteps=6)
+    g = make_grid(wl, "c128")
+    before = _run(g, wl, "c128", wl.nsteps)
+    bad = np.array(wl.abar_y, dtype=np.float64)
+    bad[2, 9] = np.nan
+    with pytest.raises(sfo.SfoError) as err:
+        g.set_vector_potential(bad)
+    assert err.value.status == E_INVALID
+    rc = sfo._lib.sfo_set_vector_potential(g._h, bad.ctypes.data_as(ctypes.c_void_p), MAX_TABLE_STEPS + 1)
+    assert rc == E_UNSUPPORTED
+    assert np.array_equal(_run(g, wl, "c128", wl.nsteps), before)
+    g.close()
+
+    # velocity gauge: a non-finite entry is refused before the length-gauge table is dropped
+    wl = W.softcore_2d_laser(n=64, nsteps=12, dt=0.05, L=20.0, E0=0.5)
+    g = make_grid(wl, "c128")
+    before = _run(g, wl, "c128", wl.nsteps)
+    abar = np.zeros((wl.nsteps, 2))
+    a2bar = np.zeros(wl.nsteps)
+    a2bar[4] = np.inf
+    with pytest.raises(sfo.SfoError) as err:
+        g.set_vector_field(abar, a2bar)
+    assert err.value.status == E_INVALID
+    assert np.array_equal(_run(g, wl, "c128", wl.nsteps), before)
+    g.close()
