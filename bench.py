@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched control line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (the reference kernel for HBM counters)")
+    p.add_argument("--library-fft", action="store_true",
+                   help="only time the torch.fft (hipFFT/rocFFT) split step of the workload (a comparison point)")
     return p.parse_args()
 
 
@@ -519,6 +521,9 @@ def main():
         copy_calibration()
         return
     wl = W.softcore_2d_laser(n=args.n)
+    if args.library_fft:
+        print(json.dumps(bench_library_fft(wl, steps=args.steps, warmup=args.warmup)))
+        return
     npts = wl.n[0] * wl.n[1]
     res = {}
     paths = [("c64", 0), ("c128", 0), ("c128_unfused", sfo.UNFUSED)]
