@@ -215,3 +215,30 @@ def test_norm_overlap(orc):
     dv = (4 / 16) * (4 / 8)
     assert abs(orc.norm(a, n, lo, hi) - dv * np.sum(np.abs(a) ** 2)) < 1e-12
     assert abs(orc.overlap(a, b, n, lo, hi) - dv * np.vdot(a, b)) < 1e-12
+
+
+# ------------------------------------------------------ free Gaussian (Sec. 5.1) --
+
+def test_free_packet_spreads_as_the_closed_form(orc):
+    """A free Gaussian packet (the paper's free-packet experiment, Sec. 5.1,
+    in its /4 width convention): with V = 0 every Strang step is the exact
+    spectral propagator, so after t the state is the textbook free packet,
+    centre x0 + hbar k0 t / m and |psi|^2 standard deviation
+    sigma sqrt(1 + (hbar t / (2 m sigma^2))^2), with the complex amplitude
+    (sigma^2 / s)^(1/2) exp(-(x - x0 - k0 t)^2 / (4 s) + i k0 x - i k0^2 t / 2),
+    s = sigma^2 + i t / 2 (hbar = m = 1)."""
+    N, L, sigma, x0, k0, dt, S = 4096, 200.0, 1.0, -20.0, 2.0, 0.01, 1000
+    x = -L + 2 * L / N * np.arange(N)
+    A = (2 * np.pi * sigma ** 2) ** -0.25
+    psi0 = A * np.exp(-(x - x0) ** 2 / (4 * sigma ** 2) + 1j * k0 * x)
+    out = orc.schrodinger(psi0, (N,), (-L,), (L,), dt, np.zeros(N), None, nsteps=S)
+    t = dt * S
+    s = sigma ** 2 + 0.5j * t
+    exact = A * np.sqrt(sigma ** 2 / s) * np.exp(-(x - x0 - k0 * t) ** 2 / (4 * s) + 1j * k0 * x - 0.5j * k0 ** 2 * t)
+    assert np.linalg.norm(out - exact) / np.linalg.norm(exact) < 1e-11
+    rho = np.abs(out) ** 2
+    rho /= rho.sum()
+    centre = (x * rho).sum()
+    width = math.sqrt(((x - centre) ** 2 * rho).sum())
+    assert abs(centre - (x0 + k0 * t)) < 1e-9
+    assert abs(width - sigma * math.sqrt(1 + (t / (2 * sigma ** 2)) ** 2)) < 1e-9
