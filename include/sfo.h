@@ -182,6 +182,7 @@ sfo_status sfo_eigenfunction(sfo_grid g, void *psi_dev, int64_t nsteps, double e
  * exp(i j dt E_e / hbar), e < nE, with dt and hbar of the grid.  chi_dev:
  * 2 * nsteps doubles, energies_dev: nE doubles, out_dev: 2 * nE doubles, all
  * device memory the caller owns; FP64.  Peaks of |out| mark eigenenergies.
+ * nE = 0 does nothing; more than 2^30 energies: SFO_E_UNSUPPORTED.
  * Asynchronous on the grid's stream. */
 sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const double *energies_dev, int32_t nE,
                         double *out_dev);

@@ -1628,6 +1628,7 @@ sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const
 {
     if (!g || !chi_dev || !energies_dev || !out_dev) return fail(SFO_E_INVALID, "null argument");
     if (nsteps < 1 || nE < 0) return fail(SFO_E_INVALID, "need nsteps >= 1 and nE >= 0");
+    if (nE > (1 << 30)) return fail(SFO_E_UNSUPPORTED, "at most 2^30 energies per call");
     HIP_TRY(launch_spectrum(chi_dev, nsteps, g->d.dt, g->d.hbar, energies_dev, nE, out_dev, g->st));
     return SFO_OK;
 }

@@ -330,7 +330,7 @@ hipError_t launch_spectrum(const double *chi, int64_t nsteps, double dt, double 
                            double *out, hipStream_t st)
 {
     if (nE <= 0 || nsteps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spectrum, dim3((unsigned)((nE + 63) / 64)), dim3(64), 0, st, chi, nsteps, dt, hbar, E, nE,
+    hipLaunchKernelGGL(k_spectrum, dim3((unsigned)(((int64_t)nE + 63) / 64)), dim3(64), 0, st, chi, nsteps, dt, hbar, E, nE,
                        out);
     return hipGetLastError();
 }

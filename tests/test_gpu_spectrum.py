@@ -99,6 +99,25 @@ def test_autocorrelation_rejects():
     g1.close()
 
 
+def test_spectrum_rejects_too_many_energies():
+    """More than 2^30 energies per call is refused before anything is read."""
+    import ctypes
+
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    wl = _wl((64, 64), 8.0, 0.05, 4)
+    g = make_grid(wl, "c128")
+    chi = torch.zeros(8, dtype=torch.float64, device="cuda")
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert sfo._lib.sfo_spectrum(g._h, ptr(chi), 4, ptr(E), (1 << 30) + 1, ptr(out)) == -2
+    assert sfo._lib.sfo_spectrum(g._h, ptr(chi), 4, ptr(E), 0, ptr(out)) == 0
+    torch.cuda.synchronize()
+    g.close()
+
+
 @pytest.mark.parametrize("dtype,n,tol", [("c128", (128, 64), 1e-10), ("c64", (128, 64), 2e-5),
                                          ("c128", (64, 64, 64), 1e-10)])
 def test_eigenfunction_matches_oracle(dtype, n, tol):
