@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched control line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (the reference kernel for HBM counters)")
+    p.add_argument("--other-workloads", action="store_true",
+                   help="only run the other workloads (1-D harmonic, 1-D Dirac, 3-D wells, 2-D Dirac)")
     p.add_argument("--library-fft", action="store_true",
                    help="only time the torch.fft (hipFFT/rocFFT) split step of the workload (a comparison point)")
     return p.parse_args()
@@ -519,6 +521,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.other_workloads:
+        print(json.dumps(bench_configs()))
         return
     wl = W.softcore_2d_laser(n=args.n)
     if args.library_fft:
