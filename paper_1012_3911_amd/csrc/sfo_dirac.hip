@@ -164,13 +164,16 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
 }
 
 // Tile shapes: radix 8 (four planes in registers), rows filling 256 threads;
-// columns: 4 adjacent lines for complex64, 2 for complex128 (within 1024
-// threads and 160 KiB of LDS).
+// columns: 4 adjacent lines (64-byte row segments of complex128), within 1024
+// threads and 160 KiB of LDS.  Complex128 holds about 240 VGPRs per thread,
+// so it keeps 4 columns only while a group stays within 512 threads (two
+// waves per SIMD) and takes 2 beyond that.
 constexpr int kDiracRad = 8;
 template <typename R, int N> constexpr int dirac_cols()
 {
-    int c = sizeof(R) == 4 ? 4 : 2;
-    while (c > 1 && (c * LineShape<N, kDiracRad>::T > 1024 || ColMap<1>::slots(N) * c * (int)sizeof(cx<R>) > 160 * 1024))
+    constexpr int T = LineShape<N, kDiracRad>::T;
+    int c = (sizeof(R) == 4 || 4 * T <= 512) ? 4 : 2;
+    while (c > 1 && (c * T > 1024 || ColMap<1>::slots(N) * c * (int)sizeof(cx<R>) > 160 * 1024))
         c /= 2;
     return c;
 }
