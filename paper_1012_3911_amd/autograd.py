@@ -17,8 +17,10 @@ import torch
 class SplitStep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, psi0, ebar, V0, grid):
-        grid.set_potential(V0.detach())
-        grid.set_field(ebar.detach().to("cpu", torch.float64).numpy())
+        v0 = V0.detach()
+        e_host = ebar.detach().to("cpu", torch.float64).numpy().copy()
+        grid.set_potential(v0)
+        grid.set_field(e_host)
         nsteps = int(ebar.shape[0])
         psi = psi0.detach().to(grid.torch_dtype).clone().contiguous()
         grid.propagate(psi, 0, nsteps)
@@ -26,13 +28,21 @@ class SplitStep(torch.autograd.Function):
         ctx.nsteps = nsteps
         ctx.ebar_meta = (ebar.device, ebar.dtype)
         ctx.v0_meta = (V0.shape, V0.dtype, V0.device)
-        ctx.save_for_backward(psi)
+        # the grid is mutable: keep what this run installed, so that a later
+        # forward call on the same grid cannot change the tables the
+        # backward of this one walks back through
+        ctx.ebar_host = e_host
+        ctx.tables = grid.tables_version
+        ctx.save_for_backward(psi, v0)
         return psi
 
     @staticmethod
     def backward(ctx, gT):
-        (psiT,) = ctx.saved_tensors
+        psiT, v0 = ctx.saved_tensors
         grid = ctx.grid
+        if grid.tables_version != ctx.tables:
+            grid.set_potential(v0)
+            grid.set_field(ctx.ebar_host)
         psi = psiT.clone()
         g = gT.detach().to(grid.torch_dtype).contiguous().clone()
         want_v = ctx.needs_input_grad[2]

@@ -1160,6 +1160,7 @@ struct sfo_batch_s {
     struct Graph {
         int dir;
         int64_t step0, nsteps;
+        std::vector<int> shapes;  // tile shapes the captured launches were made with
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;
@@ -1249,6 +1250,21 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
     return P;
 }
 
+// The tile shapes of every 2-D group's passes: a captured graph holds launches
+// of these shapes (grid sizes, and in the reverse sweep the partial-slot
+// stride of the row pass), so it is valid only while they are unchanged.
+std::vector<int> batch_shapes(const sfo_batch b)
+{
+    std::vector<int> v;
+    for (const auto &G : b->groups)
+        if (G.ndim == 2)
+            for (int ns = 1; ns <= 2; ++ns) {
+                v.push_back(row_shape(G.rep, ns));
+                v.push_back(col_shape(G.rep, 1, ns));
+            }
+    return v;
+}
+
 // The launches of one batched run on stream s (1-D whole runs on `side`
 // when it is given, joined back before the end).
 template <typename R>
@@ -1256,6 +1272,19 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
 {
     const BatchProb<R> *pd = (const BatchProb<R> *)b->probs_d;
     const int ns = dir < 0 ? 2 : 1;
+    if (dir < 0) {
+        // the reverse sweep's row work-groups write their moment partials at
+        // slot blockIdx.x of a block of gslots slots per boundary: the
+        // uploaded descriptors must have been made for these launch shapes
+        const BatchProb<R> *ph = (const BatchProb<R> *)b->probs_h.data();
+        for (const auto &G : b->groups) {
+            if (G.ndim != 2) continue;
+            const int launched = std::max(1, xpass_groups<R>(row_shape(G.rep, 2), G.nx, G.ny));
+            for (int k = 0; k < G.count; ++k)
+                if (b->probs_h.size() < sizeof(BatchProb<R>) * b->grids.size() || ph[b->ids[G.off + k]].gslots != launched)
+                    return hipErrorInvalidValue;
+        }
+    }
     const StatePtrs<R> none{{nullptr, nullptr}};
     auto grp_of = [&](const sfo_batch_s::Group &G, int64_t sa, int64_t sb, int64_t jmom, double wmul, int init) {
         GroupArgs<R> a{};
@@ -1367,8 +1396,9 @@ sfo_status batch_run(sfo_batch b, void *const *psi, void *const *gadj, int64_t s
         return SFO_OK;
     }
     hipGraphExec_t exec = nullptr;
+    const std::vector<int> shapes = batch_shapes(b);
     for (auto &gr : b->graphs)
-        if (gr.dir == dir && gr.step0 == step0 && gr.nsteps == nsteps) exec = gr.exec;
+        if (gr.dir == dir && gr.step0 == step0 && gr.nsteps == nsteps && gr.shapes == shapes) exec = gr.exec;
     if (!exec) {
         if (b->graphs.size() >= 16) {
             HIP_TRY(hipStreamSynchronize(b->st));
@@ -1385,7 +1415,7 @@ sfo_status batch_run(sfo_batch b, void *const *psi, void *const *gadj, int64_t s
         const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIP_TRY(ie);
-        b->graphs.push_back({dir, step0, nsteps, exec});
+        b->graphs.push_back({dir, step0, nsteps, shapes, exec});
     }
     HIP_TRY(hipGraphLaunch(exec, b->st));
     return SFO_OK;

@@ -177,16 +177,20 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *part, int co
         for (int w = 0; w < width; ++w) out[w] = s[w][0];
 }
 
+// max that keeps a NaN (fmax would return the other operand), so a NaN
+// anywhere in the input reaches the result and the host's finiteness check
+__device__ inline double max_keep_nan(double acc, double v) { return (v != v || v > acc) ? v : acc; }
+
 __global__ void __launch_bounds__(256) k_absmax_partial(const double *__restrict__ a, int64_t n, double *part)
 {
     __shared__ double s[256];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        acc = fmax(acc, fabs(a[i]));
+        acc = max_keep_nan(acc, fabs(a[i]));
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        if ((int)threadIdx.x < w) s[threadIdx.x] = max_keep_nan(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
@@ -196,11 +200,11 @@ __global__ void __launch_bounds__(256) k_max_partials(const double *part, int co
 {
     __shared__ double s[256];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) acc = fmax(acc, part[i]);
+    for (int i = threadIdx.x; i < count; i += 256) acc = max_keep_nan(acc, part[i]);
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+        if ((int)threadIdx.x < h) s[threadIdx.x] = max_keep_nan(s[threadIdx.x], s[threadIdx.x + h]);
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = s[0];

@@ -155,6 +155,7 @@ class Grid:
         self._h = h
         self.shape = ((self.ncomp,) if self.ncomp > 1 else ()) + self.n[::-1]
         self._keep = []
+        self.tables_version = 0  # counts successful potential / field installs
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -185,19 +186,23 @@ class Grid:
             raise ValueError("V0 must have %d values" % int(np.prod(self.n)))
         with torch.cuda.stream(self.stream):
             _check(_lib.sfo_set_potential(self._h, ctypes.c_void_p(v.data_ptr())), "sfo_set_potential")
+        self.tables_version += 1
         self._keep = [v]  # the copy is enqueued on the stream; keep the source alive until it runs
 
     def set_field(self, ebar: Optional[np.ndarray]):
         if ebar is None:
             _check(_lib.sfo_set_field(self._h, None, 0), "sfo_set_field")
+            self.tables_version += 1
             return
         e = np.ascontiguousarray(ebar, dtype=np.float64)
         if e.ndim != 2 or e.shape[1] != self.ndim:
             raise ValueError("ebar must have shape (nsteps, %d)" % self.ndim)
         _check(_lib.sfo_set_field(self._h, e.ctypes.data_as(ctypes.c_void_p), e.shape[0]), "sfo_set_field")
+        self.tables_version += 1
 
     def set_vector_field(self, abar: Optional[np.ndarray], a2bar: Optional[np.ndarray] = None):
         """Velocity gauge: per-step integrals of A(t) (nsteps, ndim) and of |A|^2 (nsteps,)."""
+        self.tables_version += 1  # a failed call may have released the field (sfo.h)
         if abar is None:
             _check(_lib.sfo_set_vector_field(self._h, None, None, 0), "sfo_set_vector_field")
             return

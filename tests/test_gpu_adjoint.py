@@ -162,3 +162,35 @@ def test_adjoint_after_autotune(orc, dtype):
     assert np.linalg.norm(gdE.cpu().numpy() - dE) / np.linalg.norm(dE) < tol
     assert np.linalg.norm((gdV.cpu().numpy() - dV).ravel()) / np.linalg.norm(dV.ravel()) < tol
     g.close()
+
+
+def test_autograd_two_forward_calls_on_one_grid(orc):
+    """Two differentiable runs with different controls on ONE grid before a single
+    backward: each run's gradient must be taken with the potential and field that
+    run used (the grid's tables are re-installed), matching the oracle."""
+    import torch
+    from paper_1012_3911_amd import autograd as AG
+
+    wl, target = problem(1, n=(512,))
+    ns = wl.nsteps
+    grid = make_grid(wl, "c128")
+    rng = np.random.default_rng(7)
+    e1 = torch.tensor(rng.uniform(-0.02, 0.02, (ns, 1)), dtype=torch.float64, requires_grad=True)
+    e2 = torch.tensor(rng.uniform(-0.02, 0.02, (ns, 1)), dtype=torch.float64, requires_grad=True)
+    V1 = torch.tensor(wl.V0, dtype=torch.float64, device="cuda", requires_grad=True)
+    V2 = torch.tensor(0.5 * wl.V0, dtype=torch.float64, device="cuda", requires_grad=True)
+    psi0 = to_device(wl.psi0, "c128")
+    tt = to_device(target, "c128")
+    L = 0.0
+    for e, V in ((e1, V1), (e2, V2)):
+        psiT = AG.propagate(psi0, e, V, grid)
+        ov = wl.dv * torch.sum(tt.conj() * psiT)
+        L = L + ov.real ** 2 + ov.imag ** 2
+    L.backward()
+    for e, V, vscale in ((e1, V1, 1.0), (e2, V2, 0.5)):
+        wl.ebar = e.detach().numpy()
+        wl.V0 = vscale * problem(1, n=(512,))[0].V0
+        _, _, _, dE, dV = oracle_grads(orc, wl, target)
+        assert np.linalg.norm(e.grad.numpy() - dE) / np.linalg.norm(dE) < 1e-9
+        assert np.linalg.norm(V.grad.cpu().numpy() - dV) / np.linalg.norm(dV) < 1e-9
+    grid.close()

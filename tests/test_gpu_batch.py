@@ -251,3 +251,160 @@ def test_control_batch_full_size(orc):
     b.close()
     for g in grids:
         g.close()
+
+
+def _amp_grad(dE, dt, hold):
+    """dL/d(amplitude k) from dL/dEbar: Ebar_s,x = dt * amp_k for the `hold` steps of piece k."""
+    return dt * dE[:, 0].reshape(-1, hold).sum(axis=1)
+
+
+def _overlap_grad(psiT, target, dv):
+    ov = dv * np.vdot(target, psiT)
+    return abs(ov) ** 2, 2 * ov * target * dv
+
+
+def test_control_batch_full_size_gradient(orc):
+    """Gradient of |<target|psi(T)>|^2 with respect to the 200 control amplitudes for
+    every problem of the 64-problem control batch (complex64, 400 steps, one batched
+    forward call and one batched reverse sweep, grids autotuned as the benchmark runs
+    them).  Checked: the norm of every problem after the forward run (drift <= 1e-6);
+    the largest 2-D problem against the complex128 single-grid adjoint and against
+    central differences of the complex128 forward run at 4 amplitudes; one 8192-point
+    line and one 256^2 problem against the oracle's stored-trajectory gradient
+    (all <= 1e-4 relative)."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls, targets, ctl = W.control_batch()
+    dt, hold, amps = ctl["dt"], ctl["hold"], ctl["control"]
+    S = wls[0].nsteps
+    grids = []
+    for wl in wls:
+        g = make_grid(wl, "c64")
+        g.autotune(3)
+        grids.append(g)
+    psis = [to_device(wl.psi0, "c64") for wl in wls]
+    n0 = [g.norm(p) for g, p in zip(grids, psis)]
+    b = sfo.Batch(grids)
+    b.propagate(psis, 0, S)
+    b.check()
+    drifts = [g.norm(p) / a - 1 for g, p, a in zip(grids, psis, n0)]
+    worst = int(np.argmax(np.abs(drifts)))
+    print("control batch: worst norm drift %.2e (problem %d, %s)" % (drifts[worst], worst, wls[worst].n),
+          flush=True)
+    gs = []
+    for wl, t, p in zip(wls, targets, psis):
+        _, gT = _overlap_grad(p.cpu().numpy().astype(np.complex128), t, wl.dv)
+        gs.append(to_device(gT, "c64"))
+    des, _ = b.adjoint(psis, gs, 0, S, want_dV0=False)
+    b.check()
+    torch.cuda.synchronize()
+    grads = [_amp_grad(d.cpu().numpy(), dt, hold) for d in des]
+    b.close()
+    for g in grids:
+        g.close()
+
+    def rel(a, ref):
+        return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+    # largest 2-D problem: complex128 single-grid adjoint and central differences
+    i2 = max((i for i, wl in enumerate(wls) if wl.ndim == 2), key=lambda i: wls[i].npoints)
+    wl = wls[i2]
+    g = make_grid(wl, "c128")
+
+    def forward(ebar):
+        g.set_field(ebar)
+        psi = to_device(wl.psi0, "c128")
+        g.propagate(psi, 0, S)
+        torch.cuda.synchronize()
+        return psi
+
+    psi = forward(wl.ebar)
+    L0, gT = _overlap_grad(psi.cpu().numpy(), targets[i2], wl.dv)
+    dE, _ = g.adjoint(psi, to_device(gT, "c128"), 0, S, want_dV0=False)
+    ref128 = _amp_grad(dE.cpu().numpy(), dt, hold)
+    e128 = rel(grads[i2], ref128)
+    print("problem %d %s: batch c64 gradient vs single-grid c128 adjoint %.2e" % (i2, wl.n, e128), flush=True)
+    assert e128 < 1e-4
+    h = 1e-5
+    scale = np.abs(ref128).max()
+    for k in (0, 57, 123, 199):
+        e_p, e_m = wl.ebar.copy(), wl.ebar.copy()
+        e_p[k * hold:(k + 1) * hold, 0] += dt * h
+        e_m[k * hold:(k + 1) * hold, 0] -= dt * h
+        Lp = _overlap_grad(forward(e_p).cpu().numpy(), targets[i2], wl.dv)[0]
+        Lm = _overlap_grad(forward(e_m).cpu().numpy(), targets[i2], wl.dv)[0]
+        fd = (Lp - Lm) / (2 * h)
+        print("  amplitude %d: FD %.6e  batch %.6e  c128 adjoint %.6e" % (k, fd, grads[i2][k], ref128[k]),
+              flush=True)
+        assert abs(fd - grads[i2][k]) <= 1e-4 * max(abs(fd), 1e-2 * scale), (k, fd, grads[i2][k])
+        assert abs(fd - ref128[k]) <= 1e-6 * max(abs(fd), 1e-2 * scale), (k, fd, ref128[k])
+    g.close()
+
+    # an 8192-point line and a 256^2 grid against the oracle's stored-trajectory gradient
+    picks = [next(i for i, w in enumerate(wls) if w.n == (8192,)), next(i for i, w in enumerate(wls) if w.n == (256, 256))]
+    for i in picks:
+        wl = wls[i]
+        psiT = oracle_run(orc, wl)
+        _, gT = _overlap_grad(psiT, targets[i], wl.dv)
+        _, dE, _ = orc.schrodinger_adjoint(wl.psi0, gT, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, wl.ebar, nsteps=S)
+        e = rel(grads[i], _amp_grad(dE, dt, hold))
+        print("problem %d %s: batch c64 gradient vs oracle %.2e" % (i, wl.n, e), flush=True)
+        assert e < 1e-4
+    assert max(abs(d) for d in drifts) < 1e-6, drifts[worst]
+
+
+def test_batch_adjoint_after_plan_change():
+    """The batch's captured reverse-sweep graph holds launches of the member grids'
+    tile shapes (grid sizes and the partial-slot stride of the row pass).  Forcing
+    other shapes on the grids between two reverse sweeps must give the same
+    gradients (complex128, 1e-12), i.e. the batch re-captures instead of replaying."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls = mixed_problems(nsteps=12)
+    grids = [make_grid(wl, "c128") for wl in wls]
+    b = sfo.Batch(grids)
+
+    def sweep():
+        psis = [to_device(wl.psi0, "c128") for wl in wls]
+        b.propagate(psis, 0, 12)
+        gs = [(0.5 * p).contiguous() for p in psis]
+        des, dvs = b.adjoint(psis, gs, 0, 12)
+        b.check()
+        torch.cuda.synchronize()
+        return [d.cpu().numpy() for d in des], [d.cpu().numpy() for d in dvs]
+
+    dE0, dV0 = sweep()
+    alts = {}
+    for i, (wl, g) in enumerate(zip(wls, grids)):
+        if wl.ndim != 2:
+            continue
+        base = g.plan
+        ok = []
+        for v in range(16):
+            if v == base[0]:
+                continue
+            try:
+                g.plan = (v, base[1], base[2])
+                ok.append(v)
+            except sfo.SfoError:
+                pass
+        g.plan = base
+        alts[i] = (base, ok)
+    changed = 0
+    for trial in range(3):
+        for i, (base, ok) in alts.items():
+            if ok:
+                grids[i].plan = (ok[trial % len(ok)], base[1], base[2])
+                changed += 1
+        dE1, dV1 = sweep()
+        for i in range(len(wls)):
+            assert np.linalg.norm(dE1[i] - dE0[i]) <= 1e-12 * np.linalg.norm(dE0[i]), (trial, i)
+            assert np.linalg.norm((dV1[i] - dV0[i]).ravel()) <= 1e-12 * np.linalg.norm(dV0[i].ravel()), (trial, i)
+    assert changed > 0
+    b.close()
+    for g in grids:
+        g.close()

@@ -211,80 +211,6 @@ def test_resume_and_reversal_device(orc):
     assert rel_l2(a, b) < 1e-14
 
 
-# ------------------------------------------------------- full-size workload --
-
-def test_2d_full_size_short_run(orc):
-    """2048^2 softcore + laser at the benchmark's size and launch configuration:
-    element-wise parity with the oracle over the first 4 steps (c128 and c64)."""
-    wl = W.softcore_2d_laser()
-    ref = oracle_run(orc, wl, nsteps=4)
-    assert rel_l2(gpu_run(wl, "c128", nsteps=4), ref) < C128_TOL
-    assert rel_l2(gpu_run(wl, "c64", nsteps=4), ref) < 1e-6
-
-
-def test_3d_full_size_short_run(orc):
-    """256^3 random wells at the benchmark's size, autotuned as the benchmark
-    runs it: element-wise parity with the oracle over the first 2 steps."""
-    import torch
-
-    wl = W.wells_3d()
-    ref = oracle_run(orc, wl, nsteps=2)
-    for dtype, tol in (("c128", C128_TOL), ("c64", 1e-6)):
-        g = make_grid(wl, dtype)
-        g.autotune(3)
-        psi = to_device(wl.psi0, dtype)
-        g.propagate(psi, 0, 2)
-        got = psi.cpu().numpy()
-        g.close()
-        del psi
-        torch.cuda.empty_cache()
-        assert rel_l2(got, ref) < tol, dtype
-
-
-def test_3d_full_size_full_run_properties():
-    """All 200 steps at 256^3: c64 agrees with c128 to the c64 tolerance, the c64 norm
-    drifts by less than 1e-6, and the c128 norm is conserved to 1e-12."""
-    import torch
-
-    wl = W.wells_3d()
-    out = {}
-    for dtype in ("c128", "c64"):
-        g = make_grid(wl, dtype)
-        g.autotune(3)
-        psi = to_device(wl.psi0, dtype)
-        n0 = g.norm(psi)
-        g.propagate(psi, 0, wl.nsteps)
-        n1 = g.norm(psi)
-        out[dtype] = (psi.cpu().numpy().astype(np.complex128), n1 / n0 - 1)
-        g.close()
-        del psi
-        torch.cuda.empty_cache()
-    assert abs(out["c128"][1]) < 1e-12
-    assert abs(out["c64"][1]) < C64_DRIFT
-    assert rel_l2(out["c64"][0], out["c128"][0]) < C64_TOL
-
-
-def test_2d_full_size_full_run_properties():
-    """All 500 steps at 2048^2: c64 agrees with c128 to the c64 tolerance, the c64 norm
-    drifts by less than 1e-6, and the c128 norm is conserved to 1e-12."""
-    import torch
-
-    wl = W.softcore_2d_laser()
-    out = {}
-    for dtype in ("c128", "c64"):
-        g = make_grid(wl, dtype)
-        psi = to_device(wl.psi0, dtype)
-        n0 = g.norm(psi)
-        g.propagate(psi, 0, wl.nsteps)
-        n1 = g.norm(psi)
-        out[dtype] = (psi.cpu().numpy().astype(np.complex128), n1 / n0 - 1)
-        g.close()
-        torch.cuda.empty_cache()
-    assert abs(out["c128"][1]) < 1e-12
-    assert abs(out["c64"][1]) < C64_DRIFT
-    assert rel_l2(out["c64"][0], out["c128"][0]) < C64_TOL
-
-
 def test_time_pass_reports_the_current_shapes():
     """sfo_time_pass: positive durations for the row and column passes of a
     2-D grid, refused for a 1-D grid (which has no separate passes)."""

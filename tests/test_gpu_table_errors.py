@@ -44,8 +44,15 @@ def test_rejected_field_and_potential_keep_the_previous_ones(dtype):
     # longer than any table a grid accepts: refused before the host array is read
     rc = sfo._lib.sfo_set_field(g._h, wl.ebar.ctypes.data_as(ctypes.c_void_p), MAX_TABLE_STEPS + 1)
     assert rc == E_UNSUPPORTED
+    for bad_value in (np.inf, -np.inf, np.nan):
+        badv = wl.V0.copy()
+        badv[3, 7] = bad_value
+        with pytest.raises(sfo.SfoError) as err:
+            g.set_potential(badv)
+        assert err.value.status == E_INVALID, bad_value
+    # a NaN in the last element and in a tail that only one reduction block sees
     badv = wl.V0.copy()
-    badv[3, 7] = np.inf
+    badv.flat[-1] = np.nan
     with pytest.raises(sfo.SfoError) as err:
         g.set_potential(badv)
     assert err.value.status == E_INVALID
