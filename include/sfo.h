@@ -198,6 +198,23 @@ sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const
 sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
                        double *dL_debar_dev, double *dL_dV0_dev);
 
+/* sfo_adjoint without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * sfo_adjoint (bit for bit); the reverse sweep's moment partials live in a
+ * static 16 MiB scratch array that each device holds until the process ends
+ * (looked up once per device by sfo_create_grid) instead of a buffer the
+ * handle allocates.  The run must fit it: 3 x (row work-groups of the
+ * two-state row pass, 1 for 1-D) x (nsteps + 1) doubles at most 2^21 (a
+ * 2048^2 grid with 1024 row work-groups fits 681 steps), else
+ * SFO_E_UNSUPPORTED before anything is enqueued.  Every call on one device
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * threads, other handles) race and give wrong gradients.  Kernel timing
+ * (sfo_profile_enable) does not cover this call.  SFO_E_HIP if the array
+ * has no device address on the grid's device.  Asynchronous. */
+sfo_status sfo_adjoint_noalloc(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
+                               double *dL_debar_dev, double *dL_dV0_dev);
+
 /* ||psi||^2 = dV sum |psi|^2 over all points and components, accumulated in
  * FP64; written to *out_host.  Synchronises the stream. */
 sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host);

@@ -20,6 +20,15 @@
 
 using namespace sfo;
 
+// Scratch memory of the allocation-free reverse sweep (sfo_adjoint_noalloc):
+// the moment partials of every step boundary, 16 MiB.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// this name only stands for the symbol: its device address on each device
+// is looked up once (scratch_setup) and only that address is passed to
+// kernels.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 21;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
 
 thread_local std::string g_err;
@@ -78,11 +87,36 @@ sfo_status upload_table(const double *host, size_t count, double **out)
     return SFO_OK;
 }
 
+// Device address of `scratch` per device (null until looked up), and the
+// error of a failed lookup.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+
+// Once per device, with that device current: look up the device address of
+// the scratch array.  A failure is remembered and reported by the entry point
+// that needs the array, not by the caller of this set-up.
+void scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev] || g_scratch_err[dev] != hipSuccess) return;
+    double *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        return;
+    }
+    g_scratch_dev[dev] = ptr;
+}
+
 }  // namespace
 
 struct sfo_grid_s {
     sfo_grid_desc d{};
     hipStream_t st = nullptr;
+    int dev = 0;  // the HIP device current at creation
     int ndim = 1;
     int ncomp = 1;
     int64_t n[3] = {1, 1, 1};
@@ -962,22 +996,23 @@ template <typename R> void default_plan(sfo_grid g)
 // (n = 0..nsteps, state psi_{step0+n}) contributes b_n = Im(conj(g_n) psi_n):
 //   dL/dV0 += (tau/2hbar) w_n b_n,  w_n = 1 at the two ends and 2 inside,
 //   mom[n] = sum_x (x, y, z) b_n,  dL/dEbar[s] = (mom[s+1] + mom[s]) / (2 hbar).
-template <typename R>
-sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV)
+// Moment partial slots per step boundary of the reverse sweep (the row
+// work-groups of its two-state row pass; 1 for 1-D), 0 if there is no shape.
+template <typename R> int adjoint_slots(const sfo_grid g)
 {
-    // moment partials: boundary n (0..nsteps) x slot x 3; the 1-D kernel writes one slot per boundary
     const int64_t nrows = g->n[1] * g->n[2];
-    const int nslots = g->ndim == 1 ? 1 : xpass_groups<R>(row_shape(g, 2), (int)g->n[0], nrows);
+    return g->ndim == 1 ? 1 : xpass_groups<R>(row_shape(g, 2), (int)g->n[0], nrows);
+}
+
+// The reverse sweep with its moment partials in `part` (at least
+// 3 adjoint_slots (nsteps + 1) doubles of device memory; every slot that
+// launch_ebar_grad reads is written first, so it needs no clearing).
+template <typename R>
+sfo_status schro_adjoint_in(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV,
+                            double *part)
+{
+    const int nslots = adjoint_slots<R>(g);
     if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
-    const int64_t need = 3 * (int64_t)nslots * (nsteps + 1);
-    if (g->part_cap < need) {
-        HIP_TRY(hipStreamSynchronize(g->st));
-        (void)hipFree(g->part);
-        g->part = nullptr;
-        g->part_cap = 0;
-        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
-        g->part_cap = need;
-    }
     const double wbase = g->d.dt / (2.0 * g->d.hbar);
     if (g->ndim == 1) {
         Run1DArgs a{};
@@ -992,7 +1027,7 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
         a.dir = -1;
         HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
             return launch_1d_adjoint<R>((int)g->n[0], (cx<R> *)psi, (cx<R> *)gv, g->V0, g->tw[0][1], a, wbase, dV,
-                                        g->part, g->st);
+                                        part, g->st);
         }));
     } else {
         GradArgs ga{};
@@ -1001,21 +1036,63 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
         auto st_of = [&](int64_t j) { return step0 + j; };
         ga.wacc = wbase;
         ga.acc_init = 1;
-        ga.part = g->part + 3 * (int64_t)nslots * nsteps;
+        ga.part = part + 3 * (int64_t)nslots * nsteps;
         const int first = nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD;
         if ((s = schro_xpass<R>(g, psi, gv, -1, nsteps > 0 ? st_of(nsteps - 1) : -1, -1, first, ga))) return s;
         for (int64_t j = nsteps - 1; j >= 0; --j) {
             if ((s = schro_colpasses<R>(g, psi, gv, M_FWD | M_KIN | M_INV, -1))) return s;
             ga.acc_init = 0;
             ga.wacc = (j > 0 ? 2.0 : 1.0) * wbase;
-            ga.part = g->part + 3 * (int64_t)nslots * j;
+            ga.part = part + 3 * (int64_t)nslots * j;
             if ((s = schro_xpass<R>(g, psi, gv, st_of(j), j > 0 ? st_of(j - 1) : -1, -1,
                                     M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), ga)))
                 return s;
         }
     }
-    if (dE) HIP_TRY(launch_ebar_grad(g->part, nslots, nsteps, g->ndim, 1.0 / (2.0 * g->d.hbar), dE, g->st));
+    if (dE) HIP_TRY(launch_ebar_grad(part, nslots, nsteps, g->ndim, 1.0 / (2.0 * g->d.hbar), dE, g->st));
     return SFO_OK;
+}
+
+// The reverse sweep with the moment partials in the handle's own buffer,
+// grown (after the stream has drained) when the run needs more.
+template <typename R>
+sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV)
+{
+    const int nslots = adjoint_slots<R>(g);
+    if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
+    const int64_t need = 3 * (int64_t)nslots * (nsteps + 1);
+    if (g->part_cap < need) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->part);
+        g->part = nullptr;
+        g->part_cap = 0;
+        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
+        g->part_cap = need;
+    }
+    return schro_adjoint_in<R>(g, psi, gv, step0, nsteps, dE, dV, g->part);
+}
+
+// The same with the partials in the device's static scratch array (see
+// sfo_adjoint_noalloc): no allocation of any kind.  Kernel timing
+// (sfo_profile_enable) is not recorded for this call, since recording it can
+// create events.
+template <typename R>
+sfo_status schro_adjoint_noalloc(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE,
+                                 double *dV, double *scratch_dev)
+{
+    const int nslots = adjoint_slots<R>(g);
+    if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
+    const int64_t need = 3 * (int64_t)nslots * (nsteps + 1);
+    if (need > kNoAllocScratchDoubles)
+        return fail(SFO_E_UNSUPPORTED,
+                    "the reverse sweep needs %lld doubles of partials (%d slots x %lld boundaries x 3), more than the "
+                    "%lld of the static scratch array; use sfo_adjoint or split the run",
+                    (long long)need, nslots, (long long)(nsteps + 1), (long long)kNoAllocScratchDoubles);
+    const bool prof = g->prof;
+    g->prof = false;
+    const sfo_status s = schro_adjoint_in<R>(g, psi, gv, step0, nsteps, dE, dV, scratch_dev);
+    g->prof = prof;
+    return s;
 }
 
 // ----------------------------------------------------------------- Dirac --
@@ -1471,6 +1548,8 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     if (!g) return fail(SFO_E_NOMEM, "host allocation failed");
     g->d = d;
     g->st = (hipStream_t)hip_stream;
+    g->dev = dev;
+    scratch_setup(dev);
     g->ndim = d.ndim;
     g->ncomp = d.equation == SFO_DIRAC ? (d.ndim == 1 ? 2 : 4) : 1;
     g->ntot = ntot;
@@ -1674,6 +1753,29 @@ sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, in
     if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the length gauge");
     return g->c128 ? schro_adjoint<double>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev)
                    : schro_adjoint<float>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev);
+}
+
+sfo_status sfo_adjoint_noalloc(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
+                               double *dL_debar_dev, double *dL_dV0_dev)
+{
+    if (!g || !psi_dev || !g_dev) return fail(SFO_E_INVALID, "null grid or state");
+    if (psi_dev == g_dev) return fail(SFO_E_INVALID, "psi and g must be distinct buffers");
+    sfo_status s = check_steps(g, step0, nsteps);
+    if (s) return s;
+    if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the Schroedinger equation");
+    if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the length gauge");
+    double *ptr = nullptr;
+    hipError_t e = hipSuccess;
+    if (g->dev >= 0 && g->dev < kMaxScratchDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ptr = g_scratch_dev[g->dev];
+        e = g_scratch_err[g->dev];
+    }
+    if (!ptr)
+        return fail(SFO_E_HIP, "the scratch array of device %d has no device address: %s", g->dev,
+                    e != hipSuccess ? hipGetErrorString(e) : "not looked up (device number out of range)");
+    return g->c128 ? schro_adjoint_noalloc<double>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev, ptr)
+                   : schro_adjoint_noalloc<float>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev, ptr);
 }
 
 sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host)

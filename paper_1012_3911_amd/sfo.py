@@ -55,7 +55,8 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
            "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
-           "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_last_error", "sfo_version"]
+           "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_adjoint_noalloc", "sfo_last_error",
+           "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
 TIME_IN_STEP = 16  # or'ed into a kernel kind: time the pass within whole steps
@@ -79,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "sfo_step": [P, P, I64],
         "sfo_propagate": [P, P, I64, I64],
         "sfo_adjoint": [P, P, P, I64, I64, P, P],
+        "sfo_adjoint_noalloc": [P, P, P, I64, I64, P, P],
         "sfo_norm": [P, P, P],
         "sfo_overlap": [P, P, P, P],
         "sfo_fft": [P, P, I32],
@@ -265,6 +267,14 @@ class Grid:
         _check(_lib.sfo_adjoint(self._h, self._state(psi), self._state(g, "g"), int(step0), int(nsteps),
                                 ctypes.c_void_p(de.data_ptr()),
                                 ctypes.c_void_p(dv.data_ptr()) if dv is not None else None), "sfo_adjoint")
+        return de, dv
+
+    def adjoint_noalloc(self, psi, g, step0: int, nsteps: int, de, dv=None):
+        """sfo_adjoint_noalloc into caller-allocated outputs de (nsteps x ndim FP64) and dv (N points FP64 or None)."""
+        _check(_lib.sfo_adjoint_noalloc(self._h, self._state(psi), self._state(g, "g"), int(step0), int(nsteps),
+                                        ctypes.c_void_p(de.data_ptr()),
+                                        ctypes.c_void_p(dv.data_ptr()) if dv is not None else None),
+               "sfo_adjoint_noalloc")
         return de, dv
 
     def norm(self, psi) -> float:

@@ -91,4 +91,5 @@ def test_null_arguments(lib):
     assert lib.sfo_spectrum(None, None, 4, None, 1, None) == -1
     assert lib.sfo_eigenfunction(None, None, 4, ctypes.c_double(0.0), None) == -1
     assert lib.sfo_set_vector_field(None, None, None, 4) == -1
+    assert lib.sfo_adjoint_noalloc(None, None, None, 0, 1, None, None) == -1
     assert lib.sfo_version().decode().startswith("sfo")
