@@ -60,10 +60,12 @@ def _load():
     lib.orc_dirac2d.argtypes = [P, P, P, D, D, D, D, D, P, P, P, I64, I64, I]
     lib.orc_schrodinger_velocity.argtypes = [I, P, P, P, D, D, D, D, P, P, P, P, I64, I64]
     lib.orc_dirac1d.argtypes = [I64, D, D, D, D, D, D, D, P, P, P, I64, I64]
+    lib.orc_schrodinger_velocity_adjoint.argtypes = [I, P, P, P, D, D, D, D, P, P, P, P, P, I64, I64, P, P, P]
     lib.orc_num_threads.restype = I
     lib.orc_set_num_threads.argtypes = [I]
     for f in (lib.orc_fft, lib.orc_norm, lib.orc_overlap, lib.orc_schrodinger,
-              lib.orc_schrodinger_adjoint, lib.orc_dirac2d, lib.orc_schrodinger_velocity, lib.orc_dirac1d):
+              lib.orc_schrodinger_adjoint, lib.orc_dirac2d, lib.orc_schrodinger_velocity, lib.orc_dirac1d,
+              lib.orc_schrodinger_velocity_adjoint):
         f.restype = I
     _lib = lib
     return lib
@@ -226,6 +228,30 @@ def schrodinger_velocity(psi0, n, xmin, xmax, dt, V0, abar, a2bar, *, step0=0, n
                                           int(nsteps))
     _check(rc, "schrodinger_velocity")
     return psi
+
+
+def schrodinger_velocity_adjoint(psi0, gT, n, xmin, xmax, dt, V0, abar, a2bar, *, step0=0, nsteps=1, mass=1.0,
+                                 hbar=1.0, charge=-1.0, want_dV0=True):
+    """Gradient through ``nsteps`` velocity-gauge steps from a stored FP64
+    trajectory, the derivative of each step's kinetic factor written out.
+    gT is 2*dL/dconj(psi_T).  Returns (g0, dL_dabar[nsteps, ndim],
+    dL_da2bar[nsteps], dL_dV0)."""
+    ndim, nn, lo, hi = _axes(n, xmin, xmax)
+    p0 = _c128(psi0)
+    g = _c128(gT).copy()
+    v = np.ascontiguousarray(V0, dtype=np.float64)
+    a = np.ascontiguousarray(abar, dtype=np.float64)
+    a2 = np.ascontiguousarray(a2bar, dtype=np.float64)
+    assert a.shape[1] == ndim and a.shape[0] >= step0 + nsteps and a2.size >= step0 + nsteps
+    da = np.zeros((nsteps, ndim))
+    da2 = np.zeros(nsteps)
+    dv = np.zeros(p0.shape) if want_dV0 else None
+    rc = _load().orc_schrodinger_velocity_adjoint(ndim, _ptr(nn), _ptr(lo), _ptr(hi), float(dt), float(mass),
+                                                  float(hbar), float(charge), _ptr(v), _ptr(a), _ptr(a2), _ptr(p0),
+                                                  _ptr(g), int(step0), int(nsteps), _ptr(da), _ptr(da2),
+                                                  _ptr(dv) if dv is not None else None)
+    _check(rc, "schrodinger_velocity_adjoint")
+    return g, da, da2, dv
 
 
 def schrodinger_adjoint(psi0, gT, n, xmin, xmax, dt, V0, ebar=None, *, step0=0, nsteps=1,

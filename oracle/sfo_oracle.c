@@ -430,6 +430,92 @@ int orc_schrodinger_adjoint(int ndim, const int64_t *n, const double *xmin, cons
     return 0;
 }
 
+/* Gradient of a real loss L(psi_T) through nsteps velocity-gauge steps
+ * (orc_schrodinger_velocity), from a STORED FP64 trajectory.  Input gT =
+ * 2 dL/d conj(psi_T); on exit g holds the same at psi_0.  With
+ * S_n = P F^-1 K_n F P and K_n = exp(-i/(2 m hbar) [tau p^2 - 2 q p.Abar_n +
+ * q^2 A2bar_n]) (p = hbar k), the derivatives of K_n are
+ *   dK_n/dAbar_{n,a} = (i q k_a / m) K_n,   dK_n/dA2bar_n = (-i q^2 / (2 m hbar)) K_n,
+ * so, written out step by step,
+ *   dL/dAbar_{n,a} = Re sum_x conj(g_{n+1}) [P F^-1 (i q k_a / m) K_n F P psi_n](x),
+ *   dL/dA2bar_n   = Re sum_x conj(g_{n+1}) [P F^-1 (-i q^2/(2 m hbar)) K_n F P psi_n](x),
+ * and dL/dV0 as in the length gauge (the half factors are the same). */
+int orc_schrodinger_velocity_adjoint(int ndim, const int64_t *n, const double *xmin, const double *xmax, double dt,
+                                     double mass, double hbar, double charge, const double *V0, const double *abar,
+                                     const double *a2bar, const cplx *psi0, cplx *g, int64_t step0, int64_t nsteps,
+                                     double *dL_dabar, double *dL_da2bar, double *dL_dV0)
+{
+    schro s;
+    if (grid_make(&s.g, ndim, n, xmin, xmax) || !V0 || !psi0 || !g || !abar || !a2bar || nsteps < 0 ||
+        step0 < 0 || !(mass > 0) || !(hbar > 0))
+        return -1;
+    s.dt = dt;
+    s.mass = mass;
+    s.hbar = hbar;
+    s.V0 = V0;
+    s.ebar = NULL;
+    s.abar = abar;
+    s.a2bar = a2bar;
+    s.charge = charge;
+    const int64_t N = s.g.ntot;
+    cplx *traj = (cplx *)malloc(sizeof(cplx) * (size_t)N * (size_t)(nsteps + 1));
+    cplx *u = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *du = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    double *im_next = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!traj || !u || !du || !im_next) {
+        free(traj), free(u), free(du), free(im_next);
+        return -2;
+    }
+    int rc = 0;
+    memcpy(traj, psi0, sizeof(cplx) * (size_t)N);
+    for (int64_t j = 0; j < nsteps && !rc; j++) {
+        memcpy(traj + (size_t)N * (j + 1), traj + (size_t)N * j, sizeof(cplx) * (size_t)N);
+        rc = schro_step(&s, traj + (size_t)N * (j + 1), step0 + j, +1);
+    }
+    if (dL_dV0) memset(dL_dV0, 0, sizeof(double) * (size_t)N);
+    {
+        const cplx *pT = traj + (size_t)N * nsteps;
+        for (int64_t i = 0; i < N; i++) im_next[i] = cimag(conj(g[i]) * pT[i]);
+    }
+    for (int64_t j = nsteps - 1; j >= 0 && !rc; j--) {
+        const int64_t step = step0 + j;
+        const cplx *pj = traj + (size_t)N * j;
+        /* K_n F P psi_n (with the 1/N of the inverse transform) */
+        memcpy(u, pj, sizeof(cplx) * (size_t)N);
+        schro_half(&s, u, step, +1);
+        if ((rc = fft_nd(u, ndim, s.g.n, -1))) break;
+        schro_kinetic(&s, u, step, +1);
+        for (int d = 0; d <= ndim; d++) {
+            /* d < ndim: the factor i q k_d / m;  d = ndim: -i q^2 / (2 m hbar) */
+            for (int64_t i = 0; i < N; i++) {
+                double k[3];
+                grid_k(&s.g, i, k);
+                const cplx f = d < ndim ? I * charge * k[d] / mass : -I * charge * charge / (2.0 * mass * hbar);
+                du[i] = f * u[i];
+            }
+            if ((rc = fft_nd(du, ndim, s.g.n, +1))) break;
+            schro_half(&s, du, step, +1);
+            double acc = 0.0;
+            for (int64_t i = 0; i < N; i++) acc += creal(conj(g[i]) * du[i]);
+            if (d < ndim) {
+                if (dL_dabar) dL_dabar[j * ndim + d] = acc;
+            } else if (dL_da2bar) {
+                dL_da2bar[j] = acc;
+            }
+        }
+        if (rc) break;
+        /* g_j = S_j^dagger g_{j+1} */
+        if ((rc = schro_step(&s, g, step, -1))) break;
+        for (int64_t i = 0; i < N; i++) {
+            const double im_here = cimag(conj(g[i]) * pj[i]);
+            if (dL_dV0) dL_dV0[i] += dt / (2.0 * hbar) * (im_next[i] + im_here);
+            im_next[i] = im_here;
+        }
+    }
+    free(traj), free(u), free(du), free(im_next);
+    return rc ? -1 : 0;
+}
+
 /* ------------------------------------------------------------ Dirac 2D --
  * Dirac representation (eq. Dirac_repr); 4-spinor stored as 4 planes. */
 

@@ -63,3 +63,105 @@ def test_zero_vector_potential_is_the_length_gauge():
     a = orc.schrodinger(psi0, (N,), (-L,), (L,), dt, V0, None, nsteps=S)
     b = orc.schrodinger_velocity(psi0, (N,), (-L,), (L,), dt, V0, np.zeros((S, 1)), np.zeros(S), nsteps=S)
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------- velocity-gauge gradient --
+
+def _vg_problem(n, S=12, dt=0.05, seed=0):
+    ndim = len(n)
+    L = 6.0
+    lo, hi = (-L,) * ndim, (L,) * ndim
+    axes = [-L + 2 * L / m * np.arange(m) for m in n]
+    X = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+    r2 = sum(x ** 2 for x in X)
+    V0 = 0.4 * r2 - 1.0 / np.sqrt(r2 + 1.0)
+    psi0 = np.exp(-r2 / 2 + 0.5j * X[0]).astype(complex)
+    psi0 /= np.sqrt(orc.norm(psi0, n, lo, hi))
+    target = np.exp(-((X[0] - 0.4) ** 2 + sum(x ** 2 for x in X[1:])) / 2).astype(complex)
+    rng = np.random.default_rng(seed)
+    abar = dt * rng.uniform(-0.8, 0.8, size=(S, ndim))
+    a2bar = dt * rng.uniform(0.0, 0.5, size=S)
+    return n, lo, hi, dt, S, V0, psi0, target, abar, a2bar
+
+
+def _vg_loss(p, abar, a2bar, V0=None):
+    n, lo, hi, dt, S, V, psi0, target, _, _ = p
+    psiT = orc.schrodinger_velocity(psi0, n, lo, hi, dt, V if V0 is None else V0, abar, a2bar, nsteps=S)
+    dv = np.prod([(hi[a] - lo[a]) / n[a] for a in range(len(n))])
+    ov = dv * np.vdot(target, psiT)
+    return abs(ov) ** 2, psiT, 2 * ov * target * dv
+
+
+def test_velocity_gradient_matches_central_differences():
+    """dL/dAbar_{n,a}, dL/dA2bar_n and dL/dV0 of |<target|psi_T>|^2 from the
+    stored trajectory against central differences of the forward run (1-D
+    and 2-D, every step and axis of Abar, several steps of A2bar and points of V0)."""
+    for n in ((64,), (32, 16)):
+        p = _vg_problem(n)
+        _, lo, hi, dt, S, V0, psi0, target, abar, a2bar = p
+        L0, psiT, gT = _vg_loss(p, abar, a2bar)
+        _, da, da2, dV = orc.schrodinger_velocity_adjoint(psi0, gT, n, lo, hi, dt, V0, abar, a2bar, nsteps=S)
+        h = 1e-6
+        for j in range(S):
+            for a in range(len(n)):
+                ap, am = abar.copy(), abar.copy()
+                ap[j, a] += h
+                am[j, a] -= h
+                fd = (_vg_loss(p, ap, a2bar)[0] - _vg_loss(p, am, a2bar)[0]) / (2 * h)
+                assert abs(fd - da[j, a]) < 1e-7 * max(1.0, np.abs(da).max()), (n, j, a, fd, da[j, a])
+        # A2bar enters each step as a global phase: a phase-blind loss does not see it
+        assert np.abs(da2).max() < 1e-12 * np.abs(da).max()
+        for j in (0, S // 2, S - 1):
+            ap, am = a2bar.copy(), a2bar.copy()
+            ap[j] += h
+            am[j] -= h
+            fd = (_vg_loss(p, abar, ap)[0] - _vg_loss(p, abar, am)[0]) / (2 * h)
+            assert abs(fd - da2[j]) < 1e-7
+        flat = V0.ravel()
+        for i in (0, flat.size // 3, flat.size // 2 + 1):
+            vp, vm = flat.copy(), flat.copy()
+            vp[i] += h
+            vm[i] -= h
+            fd = (_vg_loss(p, abar, a2bar, vp.reshape(V0.shape))[0] -
+                  _vg_loss(p, abar, a2bar, vm.reshape(V0.shape))[0]) / (2 * h)
+            assert abs(fd - dV.ravel()[i]) < 1e-7 * max(1.0, np.abs(dV).max()), (n, i)
+        assert abs(dV.sum()) < 1e-10 * np.abs(dV).sum()  # global-phase invariance
+
+
+def test_velocity_adjoint_state_is_the_transpose_of_the_run():
+    """The returned adjoint at step 0 is S^dagger applied to gT: for any state d,
+    <g0 | d> = <gT | S d> (the run is linear), exactly to rounding."""
+    p = _vg_problem((32, 16), seed=3)
+    n, lo, hi, dt, S, V0, psi0, target, abar, a2bar = p
+    rng = np.random.default_rng(11)
+    gT = rng.normal(size=psi0.shape) + 1j * rng.normal(size=psi0.shape)
+    d = rng.normal(size=psi0.shape) + 1j * rng.normal(size=psi0.shape)
+    g0, _, _, _ = orc.schrodinger_velocity_adjoint(psi0, gT, n, lo, hi, dt, V0, abar, a2bar, nsteps=S)
+    Sd = orc.schrodinger_velocity(d, n, lo, hi, dt, V0, abar, a2bar, nsteps=S)
+    lhs, rhs = np.vdot(g0, d), np.vdot(gT, Sd)
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+def test_velocity_gradient_phase_sensitive_loss():
+    """L = Re <target|psi_T> sees the global phase each step's A2bar adds:
+    dL/dA2bar_n and dL/dAbar_{n,a} against central differences."""
+    p = _vg_problem((32, 16), seed=5)
+    n, lo, hi, dt, S, V0, psi0, target, abar, a2bar = p
+    dv = np.prod([(hi[a] - lo[a]) / n[a] for a in range(2)])
+
+    def loss(ab, a2):
+        psiT = orc.schrodinger_velocity(psi0, n, lo, hi, dt, V0, ab, a2, nsteps=S)
+        return float(np.real(dv * np.vdot(target, psiT)))
+
+    _, da, da2, _ = orc.schrodinger_velocity_adjoint(psi0, dv * target, n, lo, hi, dt, V0, abar, a2bar, nsteps=S)
+    assert np.abs(da2).max() > 1e-3
+    h = 1e-6
+    for j in range(S):
+        ap, am = a2bar.copy(), a2bar.copy()
+        ap[j] += h
+        am[j] -= h
+        assert abs((loss(abar, ap) - loss(abar, am)) / (2 * h) - da2[j]) < 1e-8
+        bp, bm = abar.copy(), abar.copy()
+        bp[j, 1] += h
+        bm[j, 1] -= h
+        assert abs((loss(bp, a2bar) - loss(bm, a2bar)) / (2 * h) - da[j, 1]) < 1e-8
