@@ -59,7 +59,9 @@ typedef enum {
     SFO_E_UNSUPPORTED = -2, /* valid request the library does not implement */
     SFO_E_NOMEM = -3,       /* device allocation failed */
     SFO_E_HIP = -4,         /* HIP runtime error (no device, launch failure) */
-    SFO_E_STATE = -5        /* call out of order (e.g. no potential set) */
+    SFO_E_STATE = -5,       /* call out of order (e.g. no potential set) */
+    SFO_E_NUMERIC = -6      /* sfo_norm / sfo_overlap: a non-finite value in a state, or the
+                               norm left the band set by sfo_set_norm_watch */
 } sfo_status;
 
 enum { SFO_SCHRODINGER = 0, SFO_DIRAC = 1 };
@@ -129,9 +131,11 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps);
  * length-gauge field table; sfo_set_field (any nsteps) in turn releases these
  * tables.  nsteps = 0 clears.  Arguments are checked (SFO_E_INVALID for a
  * non-finite value) before anything changes; a failed allocation
- * (SFO_E_NOMEM) leaves the grid with no field at all.  2-D and 3-D Schroedinger grids (1-D: SFO_E_UNSUPPORTED);
- * sfo_step / sfo_propagate use it; sfo_adjoint, sfo_autocorrelation and
- * batches refuse a grid that has it (SFO_E_UNSUPPORTED). */
+ * (SFO_E_NOMEM) leaves the grid with no field at all.  Schroedinger grids of any dimension (on a 1-D
+ * grid the whole-run kernel reads step st's row of the table);
+ * sfo_step / sfo_propagate use it and sfo_adjoint_velocity differentiates
+ * it; sfo_adjoint, sfo_autocorrelation and batches refuse a grid that has it
+ * (SFO_E_UNSUPPORTED). */
 sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps);
 
 /* Copy the per-step vector-potential integrals Abar_y[step][ix] (host,
@@ -158,10 +162,12 @@ sfo_status sfo_propagate(sfo_grid g, void *psi_dev, int64_t step0, int64_t nstep
  * caller owns (may be NULL when nsteps is 0).  chi_j is formed inside the k-space pass of step j from its
  * state right after the forward transform and the stored transform of the
  * entry state (Parseval; exact because every step's first half factor is
- * the same unitary diagonal), summed in FP64 in a fixed order.  2-D and 3-D
- * Schroedinger grids (SFO_E_UNSUPPORTED otherwise) with no field table set
- * (SFO_E_UNSUPPORTED: clear it with sfo_set_field(g, NULL, 0)).  The library
- * keeps a state-sized reference buffer on the handle.  Asynchronous. */
+ * the same unitary diagonal), summed in FP64 in a fixed order; on a 1-D grid
+ * the whole run is one work-group that forms chi_j from its registers at
+ * the start of each step.  Schroedinger grids (SFO_E_UNSUPPORTED otherwise)
+ * with no field table set (SFO_E_UNSUPPORTED: clear it with
+ * sfo_set_field(g, NULL, 0)).  The library keeps a state-sized reference
+ * buffer on the handle.  Asynchronous. */
 sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double *chi_dev);
 
 /* Windowed eigenfunction of the eigenstate method (the eigenstate section,
@@ -171,7 +177,8 @@ sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double
  * psi_j, j < nsteps (unnormalised; psi_j the state after j steps), in the
  * state's dtype and layout.  The sum is accumulated in FP64 between the
  * passes of each step (a state-sized complex128 buffer the library keeps on
- * the handle) and brought to real space once at the end.  2-D and 3-D
+ * the handle) and brought to real space once at the end (1-D: each point
+ * accumulated by the thread that owns it in the whole-run kernel).
  * Schroedinger grids with no field table set (SFO_E_UNSUPPORTED otherwise);
  * psi and out distinct device buffers the caller owns.  Asynchronous. */
 sfo_status sfo_eigenfunction(sfo_grid g, void *psi_dev, int64_t nsteps, double energy, void *out_dev);
@@ -198,6 +205,23 @@ sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const
 sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
                        double *dL_debar_dev, double *dL_dV0_dev);
 
+/* Reverse-mode gradient through a velocity-gauge run (Schroedinger grids
+ * with a table set by sfo_set_vector_field; Sec. 2.2, eq. SE_K: step n's
+ * kinetic factor exp(-i/(2 m hbar) [tau p^2 - 2 q p.Abar_n + q^2 A2bar_n])).
+ * psi and g_vec as for sfo_adjoint (psi(T) and 2 dL/dconj(psi(T)) in,
+ * recomputed psi(0) and 2 dL/dconj(psi(0)) out).  Outputs, device FP64, each
+ * may be NULL, overwritten: dL_dabar_dev (nsteps x ndim, row s for step
+ * step0+s) = dL/dAbar_{s,a}; dL_da2bar_dev (nsteps) = dL/dA2bar_s; dL_dV0_dev
+ * (N points) = dL/dV0.  The gradient with respect to the step integrals is
+ * formed in momentum space inside the reverse sweep's k-space pass: with
+ * psi~ and g~ the transforms of P^-1 psi_{s+1} and P^-1 g_{s+1} there,
+ * dL/dAbar_{s,a} = -(q / (m N)) sum_k k_a Im(conj(g~) psi~) and
+ * dL/dA2bar_s = (q^2 / (2 m hbar N)) sum_k Im(conj(g~) psi~), summed in FP64
+ * per work-group and then in a fixed order.  SFO_E_STATE without a
+ * vector-field table; sfo_adjoint refuses such a grid.  Asynchronous. */
+sfo_status sfo_adjoint_velocity(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
+                                double *dL_dabar_dev, double *dL_da2bar_dev, double *dL_dV0_dev);
+
 /* sfo_adjoint without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
@@ -216,19 +240,43 @@ sfo_status sfo_adjoint_noalloc(sfo_grid g, void *psi_dev, void *g_dev, int64_t s
                                double *dL_debar_dev, double *dL_dV0_dev);
 
 /* ||psi||^2 = dV sum |psi|^2 over all points and components, accumulated in
- * FP64; written to *out_host.  Synchronises the stream. */
+ * FP64; written to *out_host (also when the status is SFO_E_NUMERIC).
+ * SFO_E_NUMERIC: the state holds a NaN or Inf (the sum is then not finite),
+ * or a norm watch is set and |norm / reference - 1| exceeds its tolerance.  Every factor of the step (Sec. 2.1, eq.
+ * U_split) is unitary, so this is the quantity a run conserves; the
+ * rectangle rule over the periodic grid is the discrete form of the L2 norm
+ * of the wave function.  Synchronises the stream. */
 sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host);
 
-/* <a|b> = dV sum conj(a) b in FP64; out_host[0] = real, out_host[1] = imaginary.
- * Synchronises the stream. */
+/* Norm watch of the handle (failure detection): from now on sfo_norm
+ * returns SFO_E_NUMERIC when |norm / reference - 1| > tolerance.  The step is
+ * unitary (Sec. 2.1), so the norm of a propagated state may only drift by
+ * rounding; a drift beyond what the precision allows (about 1e-6 over a
+ * complex64 run, 1e-12 for complex128) signals a broken run.  reference = 0
+ * switches the watch off.  SFO_E_INVALID for a negative or non-finite value. */
+sfo_status sfo_set_norm_watch(sfo_grid g, double reference, double tolerance);
+
+/* <a|b> = dV sum conj(a) b in FP64; out_host[0] = real, out_host[1] = imaginary
+ * (SFO_E_NUMERIC, with the values written, when either is not finite).
+ * With a = the state at t = 0 and b = the state at t this is the
+ * autocorrelation chi(t) of the eigenstate method (Sec. 5.2, first equation),
+ * rectangle rule over the grid; sfo_autocorrelation forms the same sum for
+ * every step of a run inside the momentum-space pass.  Synchronises the
+ * stream. */
 sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double *out_host);
 
 /* Unnormalised n-dimensional DFT of every component of psi in place,
- * exp(sign 2 pi i j m / N) along each axis, sign = -1 or +1 (the transform
- * the step uses internally; exposed for diagnostics). */
+ * exp(sign 2 pi i j m / N) along each axis, sign = -1 or +1: the transforms F
+ * (sign -1) and N F^-1 (sign +1) of eq. step_t_to_t+dt_F (Sec. 2.1), which
+ * the paper's GPU code takes from a vendor FFT library (Sec. 3.3) and which
+ * the passes here carry out with their own transforms.  Exposed for
+ * diagnostics; the step itself never calls it. */
 sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign);
 
-/* Batched runs (Schroedinger, 1-D and 2-D).  Many independent problems of
+/* Batched runs (Schroedinger, 1-D and 2-D).  The step of Sec. 2.1 (eq.
+ * step_t_to_t+dt_F) and the reverse sweep of sfo_adjoint for many problems
+ * at once; the paper propagates one wave function per run (Sec. 4.2), so
+ * the batching itself is this library's.  Many independent problems of
  * uneven size, each described by its own grid handle (its own box, time
  * step, potential, field table and tile shapes), advance together: problems
  * of one shape form a group, and each pass of the split step (Sec. 2.1, eq.
@@ -265,8 +313,11 @@ sfo_status sfo_adjoint_batch(sfo_batch b, void *const *psi_devs, void *const *g_
 sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on);
 sfo_status sfo_batch_check(sfo_batch b);
 
-/* Tile-shape planning.  Each line pass exists in several shapes (lines per
- * work-group, register radix, occupancy hint).  sfo_autotune times every
+/* Tile-shape planning.  The line passes carry the transforms F and F^-1
+ * of eq. step_t_to_t+dt_F (Sec. 2.1); the paper leaves their schedule to its
+ * vendor FFT library (Sec. 3.3), here it is chosen by measurement.  Each
+ * line pass exists in several shapes (lines per work-group, register radix,
+ * occupancy hint).  sfo_autotune times every
  * shape of every pass of this grid on a scratch state the call allocates and
  * frees (2-D and 3-D Schroedinger: `reps` whole steps of the propagation's
  * pass sequence, x shapes first with the current others, then each further
@@ -281,7 +332,9 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps);
 sfo_status sfo_get_plan(sfo_grid g, int32_t *plan3);
 sfo_status sfo_set_plan(sfo_grid g, const int32_t *plan3);
 
-/* Kernel timing (diagnostics).  While enabled, every pass the handle launches
+/* Kernel timing (diagnostics): the per-task times of the paper's
+ * performance section (Sec. 4.2: transforms with the position-space factor,
+ * transforms with the momentum-space factor).  While enabled, every pass the handle launches
  * is bracketed by a pair of HIP events recorded on the handle's stream;
  * enabling clears what was collected.  sfo_profile_read synchronises the
  * stream and returns, for one kernel kind, the number of launches and their

@@ -281,11 +281,13 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
 {
     constexpr int N1 = 4, N2 = NR / 4;
     cx<R> a[N2][N1];
-    if constexpr (std::is_same<R, float>::value) {
+    if constexpr (std::is_same<R, float>::value || PRE) {
         // complex64: W^k (read here, or PRE: read at the start of the pass,
         // pwr + i pwi); the factor of input j = j2 + N2 j1 is
         // W^{k j2} (W^{k N2})^{j1}, each formed by at most N2 - 1 + 3 + 3 FP64
-        // products from W^k
+        // products from W^k.  Complex128 with PRE (a pass that reads no table
+        // during its transforms) forms its factors the same way and applies
+        // them in FP64.
         double wr = pwr, wi = pwi;
         if constexpr (!PRE) {
             uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TW);
@@ -308,7 +310,10 @@ __device__ __forceinline__ void tw_dft(cx<R> *v, const TW *__restrict__ tw, int 
 #pragma unroll
             for (int j1 = 0; j1 < N1; ++j1) {
                 const int j = N2 * j1 + j2;
-                a[j2][j1] = j == 0 ? v[0] : mul_round(v[j], cr, ci);
+                if constexpr (std::is_same<R, float>::value)
+                    a[j2][j1] = j == 0 ? v[0] : mul_round(v[j], cr, ci);
+                else
+                    a[j2][j1] = j == 0 ? v[0] : cmul_d(v[j], cr, ci);
                 if (j1 + 1 < N1) cmul64(cr, ci, sr, si);
             }
             dft<N1, DIR>(a[j2]);
@@ -417,6 +422,20 @@ __device__ __forceinline__ void tw_base_load(TwBase<N, RAD> &w, const TwEntry<fl
     }
 }
 
+template <int N, int RAD, int S = 1>
+__device__ __forceinline__ void tw_base_load(TwBase<N, RAD> &w, const TwEntry<double> *__restrict__ tw, int t)
+{
+    using Sh = LineShape<N, RAD>;
+    if constexpr (S < Sh::NST) {
+        static_assert(Sh::RV / Sh::radix(S) == 1, "one butterfly per thread in a twiddled stage");
+        constexpr int L = Sh::span(S);
+        const TwEntry<double> e = tw[Sh::tw_offset(S) + (t & (L - 1))];
+        w.r[S - 1] = e.r;
+        w.i[S - 1] = e.i;
+        tw_base_load<N, RAD, S + 1>(w, tw, t);
+    }
+}
+
 // One Stockham stage S of an N-point transform (see the file comment).
 // v: the thread's RV cyclic values; sh: this line's LDS region; t: thread in
 // line; tw: the stage twiddle table of this (N, RAD).
@@ -444,7 +463,7 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
         const int b = t + i * T;
         const int k = b & (L - 1);
         if constexpr (L > 1 && r >= 8 && SFO_TW_GROUPED &&
-                      !(MAP::TW_AT_ONCE_FP64 && std::is_same<R, double>::value)) {
+                      (PRE || !(MAP::TW_AT_ONCE_FP64 && std::is_same<R, double>::value))) {
             constexpr int WB = S >= 1 ? S - 1 : 0;
             tw_dft<r, DIR, PRE>(u, tw, TWO, L, k, PRE ? wb.r[WB] : 0.0, PRE ? wb.i[WB] : 0.0);
         } else {
@@ -452,8 +471,9 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
                 // pins the table loads to this stage (see tw_dft)
                 uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TwEntry<R>);
                 __asm__ __volatile__("" : "+v"(kb));
-                if constexpr (std::is_same<R, float>::value) {
-                    // complex64: W^{jk} = (W^k)^j in FP64 from the one table value
+                if constexpr (std::is_same<R, float>::value || PRE) {
+                    // complex64 (and complex128 with PRE): W^{jk} = (W^k)^j in FP64
+                    // from the one table value
                     double wr, wi;
                     if constexpr (PRE) {
                         static_assert(NB == 1, "one butterfly per thread in a twiddled stage");
@@ -467,7 +487,10 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
                     double cr = wr, ci = wi;
 #pragma unroll
                     for (int j = 1; j < r; ++j) {
-                        u[j] = mul_round(u[j], cr, ci);
+                        if constexpr (std::is_same<R, float>::value)
+                            u[j] = mul_round(u[j], cr, ci);
+                        else
+                            u[j] = cmul_d(u[j], cr, ci);
                         if (j + 1 < r) cmul64(cr, ci, wr, wi);
                     }
                 } else {
@@ -540,6 +563,15 @@ __device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const
 {
     TwBase<N, RAD> unused;
     fft_line_impl<R, N, RAD, DIR, MAP, false>(v, sh, t, tw, unused, act);
+}
+
+// Either precision with the stage factors formed from wb (PRE): the
+// transforms read no table.
+template <typename R, int N, int RAD, int DIR, class MAP, int NV>
+__device__ __forceinline__ void fft_line_pre(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
+                                             const TwBase<N, RAD> &wb)
+{
+    fft_line_impl<R, N, RAD, DIR, MAP, true>(v, sh, t, tw, wb, true);
 }
 
 // The same with the stage factors of a complex64 line taken from wb.

@@ -189,7 +189,9 @@ __device__ __forceinline__ void row_load_v0(VStore<R> (&vv)[NV], const VStore<R>
 // gradient partials (mom accumulates this row's moments), forward
 // x-transform.  sh: this row's LDS exchange region; tw: twiddle table
 // (global or an LDS copy).
-template <typename R, int N, int RAD, int NS, bool PAD, int NV>
+// PRE (complex128; complex64 radix-16 rows always do it): the stage factors
+// are formed from wb, each stage's W^k read with the line.
+template <typename R, int N, int RAD, int NS, bool PAD, bool PRE = false, int NV>
 __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
                                          VStore<R> (&vv)[NV], int64_t row0, int line, int ny, cx<R> *sh, int t,
                                          const TwEntry<R> *__restrict__ tw, const TwBase<N, RAD> &wb, const PhaseArgs &ph,
@@ -207,7 +209,9 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     if (mode & M_INV)
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            if constexpr (RAD == 16)
+            if constexpr (PRE)
+                fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
+            else if constexpr (RAD == 16)
                 fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
             else
                 fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
@@ -308,14 +312,16 @@ __device__ __forceinline__ void row_body(cx<R> (&v)[NS][NV],
     if (mode & M_FWD)
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            if constexpr (RAD == 16)
+            if constexpr (PRE)
+                fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
+            else if constexpr (RAD == 16)
                 fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
             else
                 fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
         }
 }
 
-template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16), bool LATE = false>
+template <typename R, int N, int RAD, int ROWS, int NS, bool PAD = (RAD == 16), bool LATE = false, bool PRE = false>
 __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, int ny, const VStore<R> *__restrict__ V0,
                                          const TwEntry<R> *__restrict__ tw, const PhaseArgs &ph, const GradArgs &ga,
                                          int mode, cx<R> *lds, double (*red)[3], int tid)
@@ -330,19 +336,20 @@ __device__ __forceinline__ void row_tile(const StatePtrs<R> &S, int64_t row0, in
     // complex64 radix-16 rows read their stage twiddles here, with the line
     // (measured: faster for these; radix-8 rows and columns read them per stage)
     TwBase<N, RAD> wb;
-    if constexpr (std::is_same<R, float>::value && RAD == 16) tw_base_load(wb, tw, t);
+    if constexpr ((std::is_same<R, float>::value && RAD == 16) || PRE) tw_base_load(wb, tw, t);
     row_load<R, N, RAD, NS>(v, S, row0, lt);
     // the potential loads complete under the inverse transform (or, LATE, are issued after it)
     if (!LATE && (mode & M_PHASE)) row_load_v0<R, N, RAD>(vv, V0, row0, lt);
     double mom[3] = {0.0, 0.0, 0.0};
-    row_body<R, N, RAD, NS, PAD>(v, vv, row0, line, ny, sh, t, tw, wb, ph, ga, mode, mom, LATE ? V0 : nullptr);
+    row_body<R, N, RAD, NS, PAD, PRE>(v, vv, row0, line, ny, sh, t, tw, wb, ph, ga, mode, mom, LATE ? V0 : nullptr);
     // the offset is recomputed rather than held through the transforms
     __asm__ __volatile__("" : "+v"(lt));
     row_store<R, N, RAD, NS>(v, S, row0, lt);
     if (NS == 2 && (mode & M_GRAD)) block_part3(mom, red, ga.part);
 }
 
-template <typename R, int N, int RAD, int THREADS, int WPE, int NS, bool PAD = (RAD == 16), bool LATE = false>
+template <typename R, int N, int RAD, int THREADS, int WPE, int NS, bool PAD = (RAD == 16), bool LATE = false,
+          bool PRE = false>
 __global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<R> *__restrict__ tw,
         PhaseArgs ph, GradArgs ga, int mode, GroupArgs<R> grp)
@@ -351,8 +358,8 @@ k_xpass(StatePtrs<R> S, int ny, const VStore<R> *__restrict__ V0, const TwEntry<
     if (grp.probs) group_row_args<R, NS>(grp, S, V0, ph, ga);
     __shared__ cx<R> lds[ROWS * RowMap<R, RAD, PAD>::slots(N)];
     __shared__ double red[16][3];
-    row_tile<R, N, RAD, ROWS, NS, PAD, LATE>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red,
-                                             threadIdx.x);
+    row_tile<R, N, RAD, ROWS, NS, PAD, LATE, PRE>(S, (int64_t)blockIdx.x * ROWS, ny, V0, tw, ph, ga, mode, lds, red,
+                                                  threadIdx.x);
 }
 
 // ------------------------------------------------------------ column pass --
@@ -404,20 +411,31 @@ __device__ __forceinline__ void col_store(const cx<R> (&v)[NS][NV], const StateP
     }
 }
 
-// Forward transform, kinetic factor kc * kL[j] (kc: this line's factor from
-// the other axes), inverse transform.  kL: global table or an LDS copy.
-template <typename R, int N, int RAD, int C, int NS, int NV>
-__device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double kci, int sgn,
-                                         const double2 *kL, cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                         int mode)
+// Forward transform, kinetic factor kc[q] * kL[j] (kc[q]: the factor of
+// state q's line from the other axes), inverse transform.  kL: global table
+// or an LDS copy.
+// PRE: the stage factors are formed from wb (each stage's W^k, read once per
+// work-group) instead of being read from the table in every stage.
+template <typename R, int N, int RAD, int C, int NS, bool PRE = false, int NV>
+__device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], const double (&kcr)[NS], const double (&kci)[NS],
+                                         int sgn, const double2 *kL, cx<R> *sh, int t,
+                                         const TwEntry<R> *__restrict__ tw, int mode,
+                                         const TwBase<N, RAD> *wb = nullptr)
 {
     static_assert(NV == LineShape<N, RAD>::RV, "register array size must match the line shape");
     __asm__ __volatile__("" : "+v"(t));  // see row_body
     constexpr int T = LineShape<N, RAD>::T, RV = LineShape<N, RAD>::RV;
     using Map = ColMap<C>;
+    auto transform = [&](auto dir, cx<R>(&x)[NV]) {
+        constexpr int D = decltype(dir)::value;
+        if constexpr (PRE)
+            fft_line_pre<R, N, RAD, D, Map>(x, sh, t, tw, *wb);
+        else
+            fft_line<R, N, RAD, D, Map>(x, sh, t, tw);
+    };
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < NS; ++q) transform(std::integral_constant<int, -1>{}, v[q]);
     if (mode & M_KIN) {
         // index laundered after the transform: the table loads stay here
         // instead of being hoisted above it (16 FP64 pairs held through it)
@@ -426,9 +444,11 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
 #pragma unroll
         for (int m = 0; m < RV; ++m) {
             const cx<double> l = gload((const cx<double> *)((const char *)kL + m * T * (int)sizeof(double2) + tk));
-            const double kr = kcr * l.re - kci * l.im, ki = kcr * l.im + kci * l.re;
 #pragma unroll
-            for (int q = 0; q < NS; ++q) v[q][m] = mul_phase(v[q][m], kr, (double)sgn * ki);
+            for (int q = 0; q < NS; ++q) {
+                const double kr = kcr[q] * l.re - kci[q] * l.im, ki = kcr[q] * l.im + kci[q] * l.re;
+                v[q][m] = mul_phase(v[q][m], kr, (double)sgn * ki);
+            }
             // complex64: four points at a time; complex128 issues every table
             // load at once (measured faster; its register budget allows it)
             constexpr int KG = sizeof(R) == 8 ? 16 : 4;
@@ -437,27 +457,33 @@ __device__ __forceinline__ void col_body(cx<R> (&v)[NS][NV], double kcr, double 
     }
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < NS; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < NS; ++q) transform(std::integral_constant<int, +1>{}, v[q]);
 }
 
-template <typename R, int N, int RAD, int C, int NS, bool CHI>
+template <typename R, int N, int RAD, int C, int NS, bool CHI, bool VGRAD = false, bool PRE = false>
 __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int64_t slab, int64_t stride,
                                          int64_t slab_stride, const TwEntry<R> *__restrict__ tw, const KinArgs &kin,
                                          int mode, cx<R> *lds, double (*red)[3], int tid)
 {
     constexpr int RV = LineShape<N, RAD>::RV;
+    constexpr int W = C;  // lines per work-group
     const int c = tid % C, t = tid / C;
-    const int64_t col = gx * C + c;
-    const int64_t ubase = slab * slab_stride + gx * C;
+    const int64_t ubase = slab * slab_stride + gx * W;
     uint32_t tb = ((uint32_t)t * (uint32_t)stride + (uint32_t)c) * (uint32_t)sizeof(cx<R>);
     cx<R> v[NS][RV];
     col_load<R, N, RAD, NS>(v, S, ubase, stride, tb);
-    double kcr = 1.0, kci = 0.0;
-    if (mode & M_KIN) {
-        const cx<double> a = gload((const cx<double> *)kin.kA + col % kin.nA),
-                         b = gload((const cx<double> *)kin.kB + col / kin.nA);
-        kcr = a.re * b.re - a.im * b.im;
-        kci = a.re * b.im + a.im * b.re;
+    double kcr[NS], kci[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        kcr[q] = 1.0;
+        kci[q] = 0.0;
+        if (mode & M_KIN) {
+            const int64_t col = gx * W + c;
+            const cx<double> a = gload((const cx<double> *)kin.kA + col % kin.nA),
+                             b = gload((const cx<double> *)kin.kB + col / kin.nA);
+            kcr[q] = a.re * b.re - a.im * b.im;
+            kci[q] = a.re * b.im + a.im * b.re;
+        }
     }
     if constexpr (CHI) {
         // overlap of the transformed state with the reference (same layout), between the
@@ -481,6 +507,36 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
             gstore1(kin.chi_part + 2 * slot + 1, acc[1]);
         }
         col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & (M_KIN | M_INV));
+    } else if constexpr (VGRAD) {
+        // velocity-gauge gradient partials of the reverse sweep: with psi~ and g~
+        // the states right after the forward transform (k-space), the sums of
+        // (kA, kB, kL, 1) Im(conj(g~) psi~) over the work-group's points (a
+        // kernel of its own, like the overlap above)
+        static_assert(NS == 2, "gradient partials need the state and its adjoint");
+        col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & M_FWD);
+        constexpr int T = LineShape<N, RAD>::T;
+        const int64_t col = gx * W + c;
+        const double ka = kin.kvA[col % kin.nA], kb = kin.kvB ? kin.kvB[col / kin.nA] : 0.0;
+        double s1 = 0.0, sl = 0.0;
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const double b = (double)v[1][m].re * (double)v[0][m].im - (double)v[1][m].im * (double)v[0][m].re;
+            s1 += b;
+            sl += kin.kvL[t + m * T] * b;
+        }
+        double acc[3] = {ka * s1, kb * s1, sl}, acc2[3] = {s1, 0.0, 0.0};
+        block_sum3(acc, red);
+        block_sum3(acc2, red);
+        if (tid == 0) {
+            const int64_t slot = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+            for (int a = 0; a < 3; ++a) gstore1(kin.vpart + 4 * slot + a, acc[a]);
+            gstore1(kin.vpart + 4 * slot + 3, acc2[0]);
+        }
+        col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode & (M_KIN | M_INV));
+    } else if constexpr (PRE) {
+        TwBase<N, RAD> wb;
+        tw_base_load(wb, tw, t);
+        col_body<R, N, RAD, C, NS, true>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode, &wb);
     } else {
         col_body<R, N, RAD, C, NS>(v, kcr, kci, kin.sgn, kin.kL, lds + c, t, tw, mode);
     }
@@ -489,7 +545,7 @@ __device__ __forceinline__ void col_tile(const StatePtrs<R> &S, int64_t gx, int6
     col_store<R, N, RAD, NS>(v, S, ubase, stride, tb);
 }
 
-template <typename R, int N, int RAD, int C, int WPE, int NS, bool CHI = false>
+template <typename R, int N, int RAD, int C, int WPE, int NS, bool CHI = false, bool VGRAD = false, bool PRE = false>
 __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> *__restrict__ tw, KinArgs kin,
           int mode, GroupArgs<R> grp)
@@ -508,8 +564,98 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
     const unsigned G = gridDim.x * gridDim.y;
     unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
-    col_tile<R, N, RAD, C, NS, CHI>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode, lds, red,
-                                    threadIdx.x);
+    col_tile<R, N, RAD, C, NS, CHI, VGRAD, PRE>(S, L % gridDim.x, L / gridDim.x, stride, slab_stride, tw, kin, mode,
+                                                lds, red, threadIdx.x);
+}
+
+// ------------------------------------------------- pipelined column pass --
+// The k-space pass of a step (forward transform, kinetic factor, inverse
+// transform; one state) with each work-group walking column groups
+// w, w + G, w + 2G, ... (G = the grid size): the next group's loads are
+// issued while the current group transforms, so that on each CU a group's
+// memory traffic overlaps the previous group's arithmetic instead of all
+// work-groups loading, transforming and storing in lockstep.  Vector-memory
+// loads complete in order, so the transforms read no table while the
+// prefetch is in flight (a wait for a table load would also wait for every
+// load issued before it): the stage factors are formed in FP64 from each
+// stage's W^k, read once per work-group (see tw_dft), and the kinetic
+// factors of the group are requested before the prefetch.
+// ORDER 0: kinetic factors and the prefetch at the start of the group (the
+// prefetch overlaps both transforms); ORDER 1: both after the forward
+// transform (fewer registers held through it).
+template <typename R, int N, int RAD, int C, int WPE, int ORDER>
+__global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__restrict__ tw, KinArgs kin,
+          GroupArgs<R> grp)
+{
+    using Sh = LineShape<N, RAD>;
+    constexpr int T = Sh::T, RV = Sh::RV;
+    __shared__ cx<R> lds[ColMap<C>::slots(N)];
+    if (grp.probs) {
+        const BatchProb<R> &P = grp.probs[grp.ids[blockIdx.z]];
+        S.p[0] = P.psi;
+        kin.kA = P.kin_x;
+        kin.kB = P.one;
+        kin.kL = P.kin_y;
+        kin.nA = P.nx;
+    }
+    const int64_t nwg = gridDim.x;
+    int64_t w = blockIdx.x;
+    if ((nwg & 7) == 0) w = (w & 7) * (nwg >> 3) + (w >> 3);  // consecutive groups on one XCD (see k_colpass)
+    if (w >= ngroups) return;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    cx<R> *sh = lds + c;
+    uint32_t tb = ((uint32_t)t * (uint32_t)stride + (uint32_t)c) * (uint32_t)sizeof(cx<R>);
+    TwBase<N, RAD> wb;
+    tw_base_load(wb, tw, t);
+    uint32_t tk = (uint32_t)t * (uint32_t)sizeof(double2);
+    const double sg = (double)kin.sgn;
+    cx<R> a[1][RV], b[1][RV];
+    col_load<R, N, RAD, 1>(a, S, w * C, stride, tb);
+    for (int64_t j = w;;) {
+        const int64_t jn = j + nwg;
+        const bool more = jn < ngroups;
+        const int64_t col = j * C + c;
+        const cx<double> ka = gload((const cx<double> *)kin.kA + col % kin.nA),
+                         kb = gload((const cx<double> *)kin.kB + col / kin.nA);
+        cx<double> kl[RV];
+        auto load_kl = [&] {
+            __asm__ __volatile__("" : "+v"(tk));
+#pragma unroll
+            for (int m = 0; m < RV; ++m)
+                kl[m] = gload((const cx<double> *)((const char *)kin.kL + m * T * (int)sizeof(double2) + tk));
+        };
+        auto prefetch = [&] {
+            if (more) col_load<R, N, RAD, 1>(b, S, jn * C, stride, tb);
+        };
+        if constexpr (ORDER == 0) {
+            load_kl();
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch();
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        fft_line_pre<R, N, RAD, -1, ColMap<C>>(a[0], sh, t, tw, wb);
+        if constexpr (ORDER == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            load_kl();
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch();
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const double kcr = ka.re * kb.re - ka.im * kb.im, kci = ka.re * kb.im + ka.im * kb.re;
+#pragma unroll
+        for (int m = 0; m < RV; ++m) {
+            const double kr = kcr * kl[m].re - kci * kl[m].im, ki = kcr * kl[m].im + kci * kl[m].re;
+            a[0][m] = mul_phase(a[0][m], kr, sg * ki);
+        }
+        fft_line_pre<R, N, RAD, +1, ColMap<C>>(a[0], sh, t, tw, wb);
+        __asm__ __volatile__("" : "+v"(tb));
+        col_store<R, N, RAD, 1>(a, S, j * C, stride, tb);
+        if (!more) break;
+#pragma unroll
+        for (int m = 0; m < RV; ++m) a[0][m] = b[0][m];
+        j = jn;
+    }
 }
 
 // ---------------------------------------------------------------- 1-D run --
@@ -518,9 +664,18 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
 // are visited forward (dir = +1) or backward with conjugated factors
 // (dir = -1, the exact inverse).  Consecutive half steps are merged:
 //   P_first, then per step: F, K, F^-1, P_s P_next (or P_s at the end).
-template <typename R, typename VT, int N, int RAD>
+// MODE 1 (autocorrelation): at the top of step s the registers hold P psi_s
+// (P the first half factor, the same every step without a field), so
+// chi_s = dv sum conj(P psi_0)(P psi_s); each thread keeps its own points of
+// P psi_0 in a.ref (written at s = 0, read back by the same thread) and the
+// FP64 sum over the work-group is written by thread 0.  MODE 2 (windowed
+// eigenfunction): each thread accumulates tau w_s exp(i E s tau/hbar) P psi_s
+// of its points in FP64 (a.eig_acc, same-thread access), and after the run
+// writes P^-1 of the sum, exp(+i aV_half V0) acc, to a.eig_out.
+template <typename R, typename VT, int N, int RAD, int MODE = 0>
 __device__ __forceinline__ void run1d_tile(cx<R> *__restrict__ p, const VT *__restrict__ vp,
-                                           const TwEntry<R> *__restrict__ tw, const Run1DArgs &a, cx<R> *sh, int tid)
+                                           const TwEntry<R> *__restrict__ tw, const Run1DArgs &a, cx<R> *sh, int tid,
+                                           double (*red)[3] = nullptr)
 {
     using Sh = LineShape<N, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV;
@@ -551,13 +706,51 @@ __device__ __forceinline__ void run1d_tile(cx<R> *__restrict__ p, const VT *__re
         // keep the table loads inside the loop: hoisting every twiddle, kinetic
         // factor and potential value of all steps out of it exhausts registers
         __asm__ __volatile__("" ::: "memory");
+        if constexpr (MODE == 1) {
+            cx<R> *ref = (cx<R> *)a.ref;
+            double acc[3] = {0.0, 0.0, 0.0};
+            if (act)
+#pragma unroll
+                for (int m = 0; m < RV; ++m) {
+                    cx<R> r;
+                    if (s == 0) {
+                        ref[t + m * T] = v[m];
+                        r = v[m];
+                    } else {
+                        r = ref[t + m * T];
+                    }
+                    acc[0] += (double)r.re * (double)v[m].re + (double)r.im * (double)v[m].im;
+                    acc[1] += (double)r.re * (double)v[m].im - (double)r.im * (double)v[m].re;
+                }
+            block_sum3(acc, red);
+            if (tid == 0) {
+                a.chi[2 * s] = acc[0] * a.dv;
+                a.chi[2 * s + 1] = acc[1] * a.dv;
+            }
+        }
+        if constexpr (MODE == 2) {
+            const double w = a.tau * (1.0 - cospi(2.0 * (double)s / (double)a.nsteps));
+            double sn, cs;
+            sincos_fp64(a.eig_E * (double)s * a.tau / a.hbar, sn, cs);
+            const double cr = w * cs, ci = w * sn;
+            if (act)
+#pragma unroll
+                for (int m = 0; m < RV; ++m) {
+                    double2 *q = a.eig_acc + t + m * T;
+                    const double2 o = s == 0 ? double2{0.0, 0.0} : *q;
+                    const double vr = (double)v[m].re, vi = (double)v[m].im;
+                    *q = double2{o.x + cr * vr - ci * vi, o.y + cr * vi + ci * vr};
+                }
+        }
         fft_line<R, N, RAD, -1, RowMap<R, RAD>>(v, sh, t, tw, act);
-        if (act)
+        if (act) {
+            const double2 *kin = a.kin + step_of(s) * a.kin_stride;
 #pragma unroll
             for (int m = 0; m < RV; ++m) {
-                const double2 k = a.kin[t + m * T];
+                const double2 k = kin[t + m * T];
                 v[m] = mul_phase(v[m], k.x, sg * k.y);
             }
+        }
         fft_line<R, N, RAD, +1, RowMap<R, RAD>>(v, sh, t, tw, act);
         const bool more = s + 1 < a.nsteps;
         potential(a.aV_half * (more ? 2.0 : 1.0),
@@ -566,6 +759,18 @@ __device__ __forceinline__ void run1d_tile(cx<R> *__restrict__ p, const VT *__re
     if (act)
 #pragma unroll
         for (int m = 0; m < RV; ++m) p[t + m * T] = v[m];
+    if constexpr (MODE == 2) {
+        cx<R> *out = (cx<R> *)a.eig_out;
+        if (act)
+#pragma unroll
+            for (int m = 0; m < RV; ++m) {
+                const int x = t + m * T;
+                const double2 o = a.nsteps > 0 ? a.eig_acc[x] : double2{0.0, 0.0};
+                double sn, cs;
+                sincos_fp64(a.aV_half * ldv(vp + x), sn, cs);
+                out[x] = cx<R>{(R)(o.x * cs - o.y * sn), (R)(o.x * sn + o.y * cs)};
+            }
+    }
 }
 
 // Reverse sweep of a 1-D run: the state psi and its adjoint g are walked back
@@ -624,12 +829,32 @@ __device__ __forceinline__ void adj1d_tile(cx<R> *__restrict__ psi, cx<R> *__res
 #pragma unroll 1
     for (int64_t s = 0; s < a.nsteps; ++s) {
         __asm__ __volatile__("" ::: "memory");
-        for (int q = 0; q < 2; ++q) {
-            fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw, act);
+        for (int q = 0; q < 2; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw, act);
+        if (a.vmom) {
+            // velocity gauge: sum_k (k, 1) Im(conj(g~) psi~) of this step in k-space
+            double mo[3] = {0.0, 0.0, 0.0};
             if (act)
 #pragma unroll
                 for (int m = 0; m < RV; ++m) {
-                    const double2 k = a.kin[t + m * T];
+                    const double b = (double)v[1][m].re * (double)v[0][m].im - (double)v[1][m].im * (double)v[0][m].re;
+                    mo[0] += a.kv[t + m * T] * b;
+                    mo[1] += b;
+                }
+            block_sum3(mo, red);
+            if (tid == 0) {
+                double *o = a.vmom + 4 * (step_of(s) - a.step0);
+                o[0] = 0.0;
+                o[1] = 0.0;
+                o[2] = mo[0];
+                o[3] = mo[1];
+            }
+        }
+        const double2 *kin = a.kin + step_of(s) * a.kin_stride;
+        for (int q = 0; q < 2; ++q) {
+            if (act)
+#pragma unroll
+                for (int m = 0; m < RV; ++m) {
+                    const double2 k = kin[t + m * T];
                     v[q][m] = mul_phase(v[q][m], k.x, -k.y);
                 }
             fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw, act);
@@ -686,7 +911,7 @@ hipError_t row_launch(const StatePtrs<R> &S, int64_t nrows, int ny, const void *
                           dim3((unsigned)nrows, (unsigned)ngroup), dim3(LineShape<N, rv.rad>::T), st, ev, S, ny,
                           (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         } else {
-            launch_kernel(k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late>,
+            launch_kernel(k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late, rv.pre && sizeof(R) == 8>,
                           dim3((unsigned)(nrows / Tl::ROWS), (unsigned)ngroup), dim3(Tl::NT), st, ev, S, ny,
                           (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, ga, mode, grp);
         }
@@ -713,6 +938,7 @@ template <typename R, int N, int V> constexpr bool col_variant_ok()
     return cv.cols * LineShape<N, cv.rad>::T <= 1024 && ColMap<cv.cols>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024;
 }
 
+
 template <typename R, int N, int V, int NS>
 hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int nslab, int64_t slab_stride,
                       const void *const *tws, const KinArgs &kin, int mode, hipStream_t st, const GroupArgs<R> &grp,
@@ -723,6 +949,7 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
     } else {
         constexpr ColVariant cv = kColVariants[V];
         const void *tw = tws[cv.rad == 8 ? 0 : 1];
+        const bool chi = NS == 1 && (mode & M_CHI);
         if (ncols % cv.cols) return hipErrorInvalidValue;
         // per-thread byte offsets within a work-group's lines are 32-bit
         if (((int64_t)(LineShape<N, cv.rad>::T - 1) * stride + cv.cols) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
@@ -730,14 +957,36 @@ hipError_t col_launch(const StatePtrs<R> &S, int64_t ncols, int64_t stride, int 
         const dim3 grid((unsigned)(ncols / cv.cols), (unsigned)nslab, (unsigned)ngroup);
         const dim3 block(cv.cols * LineShape<N, cv.rad>::T);
         if constexpr (NS == 1) {
-            if (mode & M_CHI) {
+            if (chi) {
                 launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, 1, true>, grid, block, st, ev, S, stride,
                               slab_stride, (const TwEntry<R> *)tw, kin, mode, grp);
                 return hipGetLastError();
             }
         }
-        launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>, grid, block, st, ev, S, stride, slab_stride,
-                      (const TwEntry<R> *)tw, kin, mode, grp);
+        if constexpr (cv.pipe > 0 && NS == 1) {
+            // the k-space pass of a forward step; other modes run the plain shape
+            if (mode == (M_FWD | M_KIN | M_INV) && nslab == 1 && !chi) {
+                const int64_t ngroups = ncols / cv.cols;
+                const dim3 pgrid((unsigned)((ngroups + cv.pipe - 1) / cv.pipe), 1, (unsigned)ngroup);
+                launch_kernel(k_colpipe<R, N, cv.rad, cv.cols, cv.wpe, cv.order>, pgrid, block, st, ev, S, stride,
+                              ngroups, (const TwEntry<R> *)tw, kin, grp);
+                return hipGetLastError();
+            }
+        }
+        if constexpr (NS == 2) {
+            if (mode & M_VGRAD) {
+                launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, 2, false, true>, grid, block, st, ev, S, stride,
+                              slab_stride, (const TwEntry<R> *)tw, kin, mode, grp);
+                return hipGetLastError();
+            }
+        }
+        if constexpr (cv.pre) {
+            launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS, false, false, true>, grid, block, st, ev, S,
+                          stride, slab_stride, (const TwEntry<R> *)tw, kin, mode, grp);
+        } else {
+            launch_kernel(k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>, grid, block, st, ev, S, stride, slab_stride,
+                          (const TwEntry<R> *)tw, kin, mode, grp);
+        }
         return hipGetLastError();
     }
 }

@@ -53,10 +53,36 @@ sfo_status fail(sfo_status s, const char *fmt, ...)
                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
     } while (0)
 
-bool is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+// Debug injection of device allocation failures.  With the environment
+// variable SFO_FAIL_ALLOC=<n> set, the n-th device allocation made within one
+// ABI call on this thread (counted from 1; entry points that allocate start
+// the count with an AllocCount) fails with hipErrorOutOfMemory without
+// calling the runtime, so the error paths that release what a call had
+// allocated can be exercised.
+thread_local int t_alloc_seq = 0;
+struct AllocCount {
+    AllocCount() { t_alloc_seq = 0; }
+};
+template <typename T> hipError_t dev_malloc(T **p, size_t bytes)
+{
+    const int k = ++t_alloc_seq;
+    if (const char *e = std::getenv("SFO_FAIL_ALLOC")) {
+        if (k == std::atoi(e)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc((void **)p, bytes);
+}
 
-// Longest field or vector-potential table a grid accepts, in steps.
-constexpr int64_t kMaxTableSteps = int64_t(1) << 28;
+using check::is_pow2;
+
+// Status and reason of a host-side argument check (sfo_validate.h) as the ABI reports it.
+sfo_status checked(sfo_status s, const std::string &why)
+{
+    if (s != SFO_OK) g_err = why;
+    return s;
+}
 
 // No C++ exception crosses the C ABI: a host allocation sized by the caller
 // that fails reports SFO_E_NOMEM.
@@ -77,7 +103,7 @@ sfo_status upload_table(const double *host, size_t count, double **out)
     *out = nullptr;
     if (count == 0) return SFO_OK;
     double *d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(double) * count));
+    HIP_TRY(dev_malloc(&d, sizeof(double) * count));
     const hipError_t e = hipMemcpy(d, host, sizeof(double) * count, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(d);
@@ -152,6 +178,9 @@ struct sfo_grid_s {
     // velocity gauge: per-step, per-axis kinetic factors (vsteps x n[a] each)
     double2 *vtab[3] = {nullptr, nullptr, nullptr};
     int64_t vsteps = 0;
+    // norm watch (sfo_set_norm_watch): sfo_norm reports a relative drift from
+    // watch_ref beyond watch_tol; watch_ref = 0 is off
+    double watch_ref = 0.0, watch_tol = 0.0;
     // kernel timing: event pairs per kernel kind while profiling is on
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[SFO_KERNEL_KINDS];
@@ -270,7 +299,7 @@ sfo_status make_twiddles(sfo_grid g, int a)
         if (g->c128) {
             std::vector<TwEntry<double>> h(cnt);
             for (size_t i = 0; i < cnt; ++i) { h[i].r = cr[i]; h[i].i = ci[i]; }
-            HIP_TRY(hipMalloc(&g->tw[a][ri], sizeof(TwEntry<double>) * cnt));
+            HIP_TRY(dev_malloc(&g->tw[a][ri], sizeof(TwEntry<double>) * cnt));
             HIP_TRY(hipMemcpy(g->tw[a][ri], h.data(), sizeof(TwEntry<double>) * cnt, hipMemcpyHostToDevice));
         } else {
             std::vector<TwEntry<float>> h(cnt);
@@ -280,7 +309,7 @@ sfo_status make_twiddles(sfo_grid g, int a)
                 h[i].lr = (float)(cr[i] - (double)h[i].hr);
                 h[i].li = (float)(ci[i] - (double)h[i].hi);
             }
-            HIP_TRY(hipMalloc(&g->tw[a][ri], sizeof(TwEntry<float>) * cnt));
+            HIP_TRY(dev_malloc(&g->tw[a][ri], sizeof(TwEntry<float>) * cnt));
             HIP_TRY(hipMemcpy(g->tw[a][ri], h.data(), sizeof(TwEntry<float>) * cnt, hipMemcpyHostToDevice));
         }
     }
@@ -302,9 +331,9 @@ sfo_status make_kinetic(sfo_grid g, int a)
         h[j].x = std::cos(ph) * scale;
         h[j].y = -std::sin(ph) * scale;
     }
-    HIP_TRY(hipMalloc(&g->kin[a], sizeof(double2) * n));
+    HIP_TRY(dev_malloc(&g->kin[a], sizeof(double2) * n));
     HIP_TRY(hipMemcpy(g->kin[a], h.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&g->kvec[a], sizeof(double) * n));
+    HIP_TRY(dev_malloc(&g->kvec[a], sizeof(double) * n));
     HIP_TRY(hipMemcpy(g->kvec[a], kv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     return SFO_OK;
 }
@@ -327,7 +356,7 @@ sfo_status make_dirac1d_kinetic(sfo_grid g)
         h[(size_t)(3 * j + 1)] = {0.0, -st * c * p / E * inv};
         h[(size_t)(3 * j + 2)] = {ct * inv, st * mc2 / E * inv};
     }
-    HIP_TRY(hipMalloc(&g->du, sizeof(double2) * h.size()));
+    HIP_TRY(dev_malloc(&g->du, sizeof(double2) * h.size()));
     HIP_TRY(hipMemcpy(g->du, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
     return SFO_OK;
 }
@@ -362,7 +391,7 @@ sfo_status make_vector_tables(sfo_grid g, const double *abar, const double *a2ba
                 h[(size_t)(st * n + j)].x = std::cos(ph) * scale;
                 h[(size_t)(st * n + j)].y = -std::sin(ph) * scale;
             }
-        HIP_TRY(hipMalloc(&g->vtab[a], sizeof(double2) * h.size()));
+        HIP_TRY(dev_malloc(&g->vtab[a], sizeof(double2) * h.size()));
         HIP_TRY(hipMemcpy(g->vtab[a], h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
     }
     g->vsteps = nsteps;
@@ -449,20 +478,25 @@ sfo_status schro_xpass(sfo_grid g, void *psi, void *adj, int64_t sa, int64_t sb,
 // kstep: the step whose kinetic factor applies (velocity gauge: per-step tables).
 template <typename R>
 sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, double *chi_part = nullptr,
-                           int64_t kstep = 0)
+                           int64_t kstep = 0, double *vpart = nullptr)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const StatePtrs<R> S{{(cx<R> *)psi, (cx<R> *)adj}};
     const int ns = adj ? 2 : 1;
     const void *const *tw1 = (const void *const *)g->tw[1];
     const void *const *tw2 = (const void *const *)g->tw[2];
-    const int cmode = chi_part ? (mode | M_CHI) : mode;
+    const int cmode = (chi_part ? (mode | M_CHI) : mode) | (vpart ? M_VGRAD : 0);
     const bool vg = g->vsteps > 0;
     const double2 *kx = vg ? g->vtab[0] + kstep * nx : g->kin[0];
     const double2 *ky = vg ? g->vtab[1] + kstep * ny : g->kin[1];
     const double2 *kz = vg && g->ndim == 3 ? g->vtab[2] + kstep * nz : g->kin[2];
     if (g->ndim == 2) {
         KinArgs k{kx, g->one, ky, (int)nx, sgn, g->chi_ref, chi_part};
+        if (vpart) {
+            k.kvA = g->kvec[0];
+            k.kvL = g->kvec[1];
+            k.vpart = vpart;
+        }
         HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
             return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, 1, 0, tw1, k, cmode, g->st);
         }));
@@ -470,6 +504,12 @@ sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, 
         // 3-D: y-forward, z (forward, kinetic, inverse), y-inverse
         KinArgs none{g->one, g->one, g->one, 1, 1};
         KinArgs k{kx, ky, kz, (int)nx, sgn, g->chi_ref, chi_part};
+        if (vpart) {
+            k.kvA = g->kvec[0];
+            k.kvB = g->kvec[1];
+            k.kvL = g->kvec[2];
+            k.vpart = vpart;
+        }
         if (mode & M_FWD)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
                 return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_FWD,
@@ -478,6 +518,8 @@ sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, 
         HIP_TRY(timed(g, SFO_KERNEL_ZCOLUMN, [&] {
             return launch_colpass<R>(col_shape(g, 2, ns), (int)nz, ns, S, nx * ny, nx * ny, 1, 0, tw2, k, cmode, g->st);
         }));
+        // (the y passes around the z pass never carry the gradient partials: their
+        // mode has no M_KIN, and M_VGRAD goes only to the pass above)
         if (mode & M_INV)
             HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
                 return launch_colpass<R>(col_shape(g, 1, ns), (int)ny, ns, S, nx, nx, (int)nz, nx * ny, tw1, none, M_INV,
@@ -489,17 +531,12 @@ sfo_status schro_colpasses(sfo_grid g, void *psi, void *adj, int mode, int sgn, 
 
 sfo_status check_steps(const sfo_grid g, int64_t step0, int64_t nsteps)
 {
-    if (step0 < 0 || nsteps < 0) return fail(SFO_E_INVALID, "negative step index or count");
-    if (g->ebar_steps > 0 && step0 + nsteps > g->ebar_steps)
-        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the field table (%lld steps)", (long long)step0,
-                    (long long)(step0 + nsteps - 1), (long long)g->ebar_steps);
-    if (g->vsteps > 0 && step0 + nsteps > g->vsteps)
-        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the vector-field table (%lld steps)", (long long)step0,
-                    (long long)(step0 + nsteps - 1), (long long)g->vsteps);
-    if (g->d.equation == SFO_DIRAC && g->abar_steps > 0 && step0 + nsteps > g->abar_steps)
-        return fail(SFO_E_INVALID, "steps %lld..%lld exceed the vector-potential table (%lld steps)",
-                    (long long)step0, (long long)(step0 + nsteps - 1), (long long)g->abar_steps);
-    return SFO_OK;
+    std::string why;
+    sfo_status s = check::step_range(step0, nsteps, g->ebar_steps, "field", &why);
+    if (s == SFO_OK) s = check::step_range(step0, nsteps, g->vsteps, "vector-field", &why);
+    if (s == SFO_OK && g->d.equation == SFO_DIRAC)
+        s = check::step_range(step0, nsteps, g->abar_steps, "vector-potential", &why);
+    return checked(s, why);
 }
 
 // Schroedinger run of nsteps, forward (dir = +1) or inverse (dir = -1, last step first).
@@ -509,7 +546,9 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
     auto step_of = [&](int64_t s) { return dir > 0 ? step0 + s : step0 + nsteps - 1 - s; };
     if (g->ndim == 1) {
         Run1DArgs a{};
-        a.kin = g->kin[0];
+        // velocity gauge: step st's kinetic factors are row st of the per-step table
+        a.kin = g->vsteps > 0 ? g->vtab[0] : g->kin[0];
+        a.kin_stride = g->vsteps > 0 ? g->n[0] : 0;
         a.ebar = g->ebar_steps ? g->ebar_d : nullptr;
         a.step0 = step0;
         a.nsteps = nsteps;
@@ -557,28 +596,64 @@ template <typename R> sfo_status schro_run(sfo_grid g, void *psi, int64_t step0,
 // unnormalised transform).  The k-space pass of step j holds F P psi_j right
 // after its forward transform and forms the overlap with the stored F P psi_0
 // there: FP64 partials per work-group, summed in slot order afterwards.
+// Arguments of a 1-D eigenstate run (time-independent potential, forward).
+Run1DArgs eigen1d_args(const sfo_grid g, int64_t nsteps)
+{
+    Run1DArgs a{};
+    a.kin = g->kin[0];
+    a.step0 = 0;
+    a.nsteps = nsteps;
+    a.aV_half = g->d.dt / (2.0 * g->d.hbar);
+    a.inv_2hbar = 1.0 / (2.0 * g->d.hbar);
+    a.xmin = g->d.xmin[0];
+    a.dx = g->dx[0];
+    a.dir = 1;
+    a.tau = g->d.dt;
+    a.hbar = g->d.hbar;
+    a.dv = g->dv;
+    return a;
+}
+
+// A state-sized buffer of the handle for the eigenstate runs' reference state.
+sfo_status ensure_chi_ref(sfo_grid g, size_t sbytes)
+{
+    if (g->chi_ref_bytes >= sbytes) return SFO_OK;
+    HIP_TRY(hipStreamSynchronize(g->st));
+    (void)hipFree(g->chi_ref);
+    g->chi_ref = nullptr;
+    g->chi_ref_bytes = 0;
+    HIP_TRY(dev_malloc(&g->chi_ref, sbytes));
+    g->chi_ref_bytes = sbytes;
+    return SFO_OK;
+}
+
 template <typename R> sfo_status schro_autocorr(sfo_grid g, void *psi, int64_t nsteps, double *chi)
 {
     if (nsteps == 0) return SFO_OK;
+    if (g->ndim == 1) {
+        // the whole run in one work-group; chi_j written by the kernel itself
+        sfo_status s = ensure_chi_ref(g, sizeof(cx<R>) * (size_t)g->ntot);
+        if (s) return s;
+        Run1DArgs a = eigen1d_args(g, nsteps);
+        a.chi = chi;
+        a.ref = g->chi_ref;
+        HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
+            return launch_1d_eigen<R>((int)g->n[0], (cx<R> *)psi, g->V0, g->tw[0][1], a, g->st);
+        }));
+        return SFO_OK;
+    }
     const int kax = g->ndim - 1;
     const int64_t ncols = kax == 1 ? g->n[0] : g->n[0] * g->n[1];
     const int nslots = (int)(ncols / kColVariants[col_shape(g, kax, 1)].cols);
     const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
-    if (g->chi_ref_bytes < sbytes) {
-        HIP_TRY(hipStreamSynchronize(g->st));
-        (void)hipFree(g->chi_ref);
-        g->chi_ref = nullptr;
-        g->chi_ref_bytes = 0;
-        HIP_TRY(hipMalloc(&g->chi_ref, sbytes));
-        g->chi_ref_bytes = sbytes;
-    }
+    if (sfo_status s0 = ensure_chi_ref(g, sbytes)) return s0;
     const int64_t need = 2 * (int64_t)nslots * nsteps;
     if (g->part_cap < need) {
         HIP_TRY(hipStreamSynchronize(g->st));
         (void)hipFree(g->part);
         g->part = nullptr;
         g->part_cap = 0;
-        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
+        HIP_TRY(dev_malloc(&g->part, sizeof(double) * need));
         g->part_cap = need;
     }
     // reference F P psi_0: the run's first row pass and the forward transforms of the other axes
@@ -611,7 +686,19 @@ template <typename R> sfo_status schro_autocorr(sfo_grid g, void *psi, int64_t n
 template <typename R> sfo_status schro_eigen(sfo_grid g, void *psi, int64_t nsteps, double E, void *out)
 {
     const int64_t n = g->ntot;
-    if (!g->eig_acc) HIP_TRY(hipMalloc(&g->eig_acc, sizeof(double2) * (size_t)n));
+    if (!g->eig_acc) HIP_TRY(dev_malloc(&g->eig_acc, sizeof(double2) * (size_t)n));
+    if (g->ndim == 1) {
+        // the whole run in one work-group: the sum accumulated per point in
+        // FP64 by the thread that owns it, P^-1 applied at the end
+        Run1DArgs a = eigen1d_args(g, nsteps);
+        a.eig_acc = g->eig_acc;
+        a.eig_out = out;
+        a.eig_E = E;
+        HIP_TRY(timed(g, SFO_KERNEL_LINE1D, [&] {
+            return launch_1d_eigen<R>((int)g->n[0], (cx<R> *)psi, g->V0, g->tw[0][1], a, g->st);
+        }));
+        return SFO_OK;
+    }
     HIP_TRY(hipMemsetAsync(g->eig_acc, 0, sizeof(double2) * (size_t)n, g->st));
     const double tau = g->d.dt, hb = g->d.hbar;
     sfo_status s;
@@ -814,7 +901,7 @@ struct TimingScratch {
 template <typename R> sfo_status timing_setup(sfo_grid g, TimingScratch &ts)
 {
     const size_t bytes = sizeof(cx<R>) * (size_t)g->ntot * g->ncomp;
-    HIP_TRY(hipMalloc(&ts.mem, bytes));
+    HIP_TRY(dev_malloc(&ts.mem, bytes));
     HIP_TRY(hipMemsetAsync(ts.mem, 0, bytes, g->st));
     HIP_TRY(hipEventCreate(&ts.a));
     HIP_TRY(hipEventCreate(&ts.b));
@@ -860,7 +947,7 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
                 b = 1e30;
                 int keep = cv[ax];
                 for (int v = 0; v < kNumColVariants; ++v) {
-                    if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+                    if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, ns)) continue;
                     cv[ax] = v;
                     const double ms = best_of([&] { return steps(rv, cv); });
                     if (ms >= 0 && ms < b) { b = ms; keep = v; }
@@ -877,11 +964,11 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
         const size_t ebytes = sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows);
         void *extra = nullptr;
-        HIP_TRY(hipMalloc(&extra, ebytes));
+        HIP_TRY(dev_malloc(&extra, ebytes));
         hipError_t he = hipMemsetAsync(extra, 0, ebytes, g->st);
         if (he == hipSuccess) {
             double *acc = (double *)((char *)extra + sbytes);
-            int rv2 = g->row_var, cv2[3] = {0, g->col_var[1], g->col_var[2]};
+            int rv2 = g->row_var, cv2[3] = {0, col_shape(g, 1, 2), g->ndim == 3 ? col_shape(g, 2, 2) : 0};
             tune(2, rv2, cv2, (cx<R> *)extra, acc, acc + g->ntot);
             g->row_var2 = rv2;
             g->col_var2[1] = cv2[1];
@@ -911,7 +998,7 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
     const int64_t nrows = g->n[1] * g->n[2];
     const size_t sbytes = sizeof(cx<R>) * (size_t)g->ntot;
     void *extra = nullptr;
-    HIP_TRY(hipMalloc(&extra, sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows)));
+    HIP_TRY(dev_malloc(&extra, sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows)));
     hipError_t he = hipMemsetAsync(extra, 0, sbytes + sizeof(double) * (size_t)(g->ntot + 3 * nrows), g->st);
     cx<R> *adj = (cx<R> *)extra;
     double *acc = (double *)((char *)extra + sbytes);
@@ -927,7 +1014,7 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
             const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
             best = 1e30;
             for (int v = 0; v < kNumColVariants; ++v) {
-                if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+                if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, 2)) continue;
                 const double ms = best_of([&] { return time_col2<R>(g, ax, v, psi, adj, ts.a, ts.b, reps); });
                 if (ms >= 0 && ms < best) { best = ms; g->col_var2[ax] = v; }
             }
@@ -1007,16 +1094,23 @@ template <typename R> int adjoint_slots(const sfo_grid g)
 // The reverse sweep with its moment partials in `part` (at least
 // 3 adjoint_slots (nsteps + 1) doubles of device memory; every slot that
 // launch_ebar_grad reads is written first, so it needs no clearing).
+// Velocity gauge (vpart != null): each step's k-space pass uses that step's
+// kinetic tables and writes the gradient partials of the step (vslots x 4
+// doubles per step, see KinArgs) to vpart.
 template <typename R>
 sfo_status schro_adjoint_in(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dE, double *dV,
-                            double *part)
+                            double *part, double *vpart = nullptr, int vslots = 0)
 {
     const int nslots = adjoint_slots<R>(g);
     if (nslots < 1) return fail(SFO_E_STATE, "no row pass shape for this grid");
     const double wbase = g->d.dt / (2.0 * g->d.hbar);
+    const bool vg = g->vsteps > 0;
     if (g->ndim == 1) {
         Run1DArgs a{};
-        a.kin = g->kin[0];
+        a.kin = vg ? g->vtab[0] : g->kin[0];
+        a.kin_stride = vg ? g->n[0] : 0;
+        a.kv = g->kvec[0];
+        a.vmom = vpart;
         a.ebar = g->ebar_steps ? g->ebar_d : nullptr;
         a.step0 = step0;
         a.nsteps = nsteps;
@@ -1040,7 +1134,9 @@ sfo_status schro_adjoint_in(sfo_grid g, void *psi, void *gv, int64_t step0, int6
         const int first = nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD;
         if ((s = schro_xpass<R>(g, psi, gv, -1, nsteps > 0 ? st_of(nsteps - 1) : -1, -1, first, ga))) return s;
         for (int64_t j = nsteps - 1; j >= 0; --j) {
-            if ((s = schro_colpasses<R>(g, psi, gv, M_FWD | M_KIN | M_INV, -1))) return s;
+            if ((s = schro_colpasses<R>(g, psi, gv, M_FWD | M_KIN | M_INV, -1, nullptr, st_of(j),
+                                        vpart ? vpart + 4 * (int64_t)vslots * j : nullptr)))
+                return s;
             ga.acc_init = 0;
             ga.wacc = (j > 0 ? 2.0 : 1.0) * wbase;
             ga.part = part + 3 * (int64_t)nslots * j;
@@ -1066,10 +1162,47 @@ sfo_status schro_adjoint(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t
         (void)hipFree(g->part);
         g->part = nullptr;
         g->part_cap = 0;
-        HIP_TRY(hipMalloc(&g->part, sizeof(double) * need));
+        HIP_TRY(dev_malloc(&g->part, sizeof(double) * need));
         g->part_cap = need;
     }
     return schro_adjoint_in<R>(g, psi, gv, step0, nsteps, dE, dV, g->part);
+}
+
+// Work-groups of the reverse sweep's k-space pass (its velocity-gauge
+// partial slots; 1 for 1-D).
+template <typename R> int vgrad_slots(const sfo_grid g)
+{
+    if (g->ndim == 1) return 1;
+    const int ax = g->ndim - 1;
+    const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
+    return (int)(ncols / kColVariants[col_shape(g, ax, 2)].cols);
+}
+
+// Reverse sweep of a velocity-gauge run (sfo_adjoint_velocity): the row
+// moment partials (unused here: no field table) and the k-space partials in
+// the handle's buffer, then dL/dAbar = -q/(m N) sum_k k_a Im(conj(g~) psi~)
+// and dL/dA2bar = q^2/(2 m hbar N) sum_k Im(conj(g~) psi~) per step.
+template <typename R>
+sfo_status schro_adjoint_velocity(sfo_grid g, void *psi, void *gv, int64_t step0, int64_t nsteps, double *dA,
+                                  double *dA2, double *dV)
+{
+    const int nslots = adjoint_slots<R>(g), vslots = vgrad_slots<R>(g);
+    if (nslots < 1 || vslots < 1) return fail(SFO_E_STATE, "no pass shape for this grid");
+    const int64_t nrow = 3 * (int64_t)nslots * (nsteps + 1), need = nrow + 4 * (int64_t)vslots * nsteps;
+    if (g->part_cap < need) {
+        HIP_TRY(hipStreamSynchronize(g->st));
+        (void)hipFree(g->part);
+        g->part = nullptr;
+        g->part_cap = 0;
+        HIP_TRY(dev_malloc(&g->part, sizeof(double) * need));
+        g->part_cap = need;
+    }
+    double *vpart = g->part + nrow;
+    sfo_status s = schro_adjoint_in<R>(g, psi, gv, step0, nsteps, nullptr, dV, g->part, vpart, vslots);
+    if (s) return s;
+    const double q = g->d.charge, m = g->d.mass, hb = g->d.hbar, N = (double)g->ntot;
+    HIP_TRY(launch_vgrad_sum(vpart, vslots, nsteps, g->ndim, -q / (m * N), q * q / (2.0 * m * hb * N), dA, dA2, g->st));
+    return SFO_OK;
 }
 
 // The same with the partials in the device's static scratch array (see
@@ -1457,7 +1590,7 @@ sfo_status batch_run(sfo_batch b, void *const *psi, void *const *gadj, int64_t s
         (void)hipFree(b->work);
         b->work = nullptr;
         b->work_cap = 0;
-        HIP_TRY(hipMalloc(&b->work, sizeof(double) * need));
+        HIP_TRY(dev_malloc(&b->work, sizeof(double) * need));
         b->work_cap = need;
     }
     const std::vector<BatchProb<R>> P = batch_probs<R>(b, psi, gadj, dE, dV, nsteps, &need);
@@ -1508,36 +1641,14 @@ const char *sfo_version(void) { return "sfo 0.1 (gfx950)"; }
 
 sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid *out)
 {
+    AllocCount alloc_count;
     g_err.clear();
     if (!desc || !out) return fail(SFO_E_INVALID, "null descriptor or output handle");
     *out = nullptr;
     const sfo_grid_desc &d = *desc;
-    if (d.ndim < 1 || d.ndim > 3) return fail(SFO_E_INVALID, "ndim must be 1, 2 or 3 (got %d)", d.ndim);
-    if (d.equation != SFO_SCHRODINGER && d.equation != SFO_DIRAC)
-        return fail(SFO_E_INVALID, "unknown equation %d", d.equation);
-    if (d.dtype != SFO_C64 && d.dtype != SFO_C128) return fail(SFO_E_INVALID, "unknown dtype %d", d.dtype);
-    if (!(d.dt > 0) || !std::isfinite(d.dt)) return fail(SFO_E_INVALID, "dt must be positive and finite");
-    if (!(d.hbar > 0) || !(d.mass > 0)) return fail(SFO_E_INVALID, "hbar and mass must be positive");
-    if (d.equation == SFO_DIRAC && (d.ndim > 2 || !(d.c > 0)))
-        return fail(SFO_E_INVALID, "Dirac needs ndim 1 or 2 and c > 0");
     int64_t ntot = 1;
-    for (int a = 0; a < d.ndim; ++a) {
-        if (!is_pow2(d.n[a])) return fail(SFO_E_INVALID, "n[%d] = %lld is not a power of two", a, (long long)d.n[a]);
-        if (!(d.xmax[a] > d.xmin[a]) || !std::isfinite(d.xmin[a]) || !std::isfinite(d.xmax[a]))
-            return fail(SFO_E_INVALID, "axis %d: need finite xmin < xmax", a);
-        const int64_t maxn = d.ndim == 1 ? kMax1DN : kMaxPassN;
-        if (d.n[a] < kMinN || d.n[a] > maxn)
-            return fail(SFO_E_UNSUPPORTED, "n[%d] = %lld outside the supported %d..%lld", a, (long long)d.n[a], kMinN,
-                        (long long)maxn);
-        ntot *= d.n[a];
-    }
-    // the line passes address a work-group's lines by 32-bit byte offsets from
-    // a scalar base: at most (N / 8) lines of stride <= plane / N apart, below
-    // 2^32 for a state plane of at most 2^35 bytes
-    const int64_t plane_bytes = ntot * (d.dtype == SFO_C128 ? 16 : 8);
-    if (plane_bytes > ((int64_t)1 << 35))
-        return fail(SFO_E_UNSUPPORTED, "a state of %lld bytes per component exceeds the 32 GiB the passes address",
-                    (long long)plane_bytes);
+    std::string why;
+    if (sfo_status vs = check::grid_desc(desc, &why, &ntot)) return checked(vs, why);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     int ndev = 0;
@@ -1571,11 +1682,11 @@ sfo_status sfo_create_grid(const sfo_grid_desc *desc, void *hip_stream, sfo_grid
     if (s == SFO_OK && d.equation == SFO_DIRAC && d.ndim == 1) s = no_throw([&] { return make_dirac1d_kinetic(g); });
     if (s != SFO_OK) return guard(s);
     const double2 one = {1.0, 0.0};
-    hipError_t he = hipMalloc(&g->one, sizeof(double2));
+    hipError_t he = dev_malloc(&g->one, sizeof(double2));
     if (he == hipSuccess) he = hipMemcpy(g->one, &one, sizeof(double2), hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMalloc(&g->red, sizeof(double) * (2 * kReduceBlocks + 4));
+    if (he == hipSuccess) he = dev_malloc(&g->red, sizeof(double) * (2 * kReduceBlocks + 4));
     const size_t vbytes = (g->c128 ? sizeof(double) : sizeof(float)) * (size_t)ntot;
-    if (he == hipSuccess) he = hipMalloc(&g->V0, vbytes);
+    if (he == hipSuccess) he = dev_malloc(&g->V0, vbytes);
     if (he == hipSuccess) he = hipMemset(g->V0, 0, vbytes);
     if (he != hipSuccess)
         return guard(fail(he == hipErrorOutOfMemory ? SFO_E_NOMEM : SFO_E_HIP, "allocation: %s", hipGetErrorString(he)));
@@ -1608,14 +1719,13 @@ sfo_status sfo_set_potential(sfo_grid g, const double *V0_dev)
 
 sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
 {
+    AllocCount alloc_count;
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "field table is for the Schroedinger equation");
-    if (nsteps < 0 || (nsteps > 0 && !ebar_host)) return fail(SFO_E_INVALID, "bad field table");
-    if (nsteps > kMaxTableSteps)
-        return fail(SFO_E_UNSUPPORTED, "field tables hold at most %lld steps", (long long)kMaxTableSteps);
+    std::string why;
+    if (sfo_status vs = check::step_table(ebar_host, nsteps, g->ndim, 0.0, 0.0, "field", &why))
+        return checked(vs, why);
     const size_t count = (size_t)nsteps * g->ndim;
-    for (size_t i = 0; i < count; ++i)
-        if (!std::isfinite(ebar_host[i])) return fail(SFO_E_INVALID, "field table holds a non-finite value");
     return no_throw([&]() -> sfo_status {
         std::vector<double> host(ebar_host, ebar_host + count);
         double *dev = nullptr;
@@ -1639,19 +1749,18 @@ sfo_status sfo_set_field(sfo_grid g, const double *ebar_host, int64_t nsteps)
 
 sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const double *a2bar_host, int64_t nsteps)
 {
+    AllocCount alloc_count;
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_INVALID, "the vector field is for the Schroedinger equation");
-    if (nsteps < 0 || (nsteps > 0 && (!abar_host || !a2bar_host))) return fail(SFO_E_INVALID, "bad vector-field table");
-    if (nsteps > 0 && g->ndim < 2)
-        return fail(SFO_E_UNSUPPORTED, "the velocity gauge is built for 2-D and 3-D grids");
     int64_t per = 0;
     for (int a = 0; a < g->ndim; ++a) per += g->n[a];
-    if (nsteps > kMaxTableSteps || (double)nsteps * (double)per * sizeof(double2) > (double)(1ll << 30))
+    std::string why;
+    sfo_status vs = check::step_table(abar_host, nsteps, g->ndim, 0.0, 0.0, "vector-field", &why);
+    if (vs == SFO_OK) vs = check::step_table(a2bar_host, nsteps, 1, 0.0, 0.0, "vector-field", &why);
+    if (vs) return checked(vs, why);
+    // the device tables: per-step, per-axis complex factors, nsteps x (n[0] + n[1] + n[2]) x 16 bytes
+    if ((double)nsteps * (double)per * sizeof(double2) > kMaxTableBytes)
         return fail(SFO_E_UNSUPPORTED, "vector-field tables of %lld steps exceed 1 GiB", (long long)nsteps);
-    for (int64_t i = 0; i < nsteps * g->ndim; ++i)
-        if (!std::isfinite(abar_host[i])) return fail(SFO_E_INVALID, "vector-field table holds a non-finite value");
-    for (int64_t i = 0; i < nsteps; ++i)
-        if (!std::isfinite(a2bar_host[i])) return fail(SFO_E_INVALID, "vector-field table holds a non-finite value");
     HIP_TRY(hipStreamSynchronize(g->st));
     release_vector_tables(g);
     // the velocity gauge replaces the length-gauge field
@@ -1668,14 +1777,14 @@ sfo_status sfo_set_vector_field(sfo_grid g, const double *abar_host, const doubl
 
 sfo_status sfo_set_vector_potential(sfo_grid g, const double *abar_y_host, int64_t nsteps)
 {
+    AllocCount alloc_count;
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (g->d.equation != SFO_DIRAC) return fail(SFO_E_INVALID, "vector potential is for the Dirac equation");
-    if (nsteps < 0 || (nsteps > 0 && !abar_y_host)) return fail(SFO_E_INVALID, "bad vector-potential table");
-    if (nsteps > kMaxTableSteps || (double)nsteps * (double)g->n[0] * sizeof(double) > (double)(1ll << 30))
-        return fail(SFO_E_UNSUPPORTED, "vector-potential tables of %lld steps exceed 1 GiB", (long long)nsteps);
+    std::string why;
+    if (sfo_status vs = check::step_table(abar_y_host, nsteps, g->n[0], sizeof(double), kMaxTableBytes,
+                                          "vector-potential", &why))
+        return checked(vs, why);
     const size_t count = (size_t)nsteps * g->n[0];
-    for (size_t i = 0; i < count; ++i)
-        if (!std::isfinite(abar_y_host[i])) return fail(SFO_E_INVALID, "vector-potential table holds a non-finite value");
     return no_throw([&]() -> sfo_status {
         std::vector<double> host(abar_y_host, abar_y_host + count);
         double *dev = nullptr;
@@ -1709,10 +1818,11 @@ sfo_status sfo_step(sfo_grid g, void *psi_dev, int64_t step_index) { return sfo_
 
 sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double *chi_dev)
 {
+    AllocCount alloc_count;
     if (!g || !psi_dev || (!chi_dev && nsteps > 0)) return fail(SFO_E_INVALID, "null grid, state or output");
     if (nsteps < 0) return fail(SFO_E_INVALID, "negative step count");
-    if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
-        return fail(SFO_E_UNSUPPORTED, "the autocorrelation run is built for 2-D and 3-D Schroedinger grids");
+    if (g->d.equation != SFO_SCHRODINGER)
+        return fail(SFO_E_UNSUPPORTED, "the autocorrelation run is built for Schroedinger grids");
     if (g->ebar_steps > 0 || g->vsteps > 0)
         return fail(SFO_E_UNSUPPORTED, "the autocorrelation run needs a time-independent potential: clear the field table");
     return g->c128 ? schro_autocorr<double>(g, psi_dev, nsteps, chi_dev)
@@ -1721,11 +1831,12 @@ sfo_status sfo_autocorrelation(sfo_grid g, void *psi_dev, int64_t nsteps, double
 
 sfo_status sfo_eigenfunction(sfo_grid g, void *psi_dev, int64_t nsteps, double energy, void *out_dev)
 {
+    AllocCount alloc_count;
     if (!g || !psi_dev || !out_dev) return fail(SFO_E_INVALID, "null grid, state or output");
     if (psi_dev == out_dev) return fail(SFO_E_INVALID, "psi and the output must be distinct buffers");
     if (nsteps < 0 || !std::isfinite(energy)) return fail(SFO_E_INVALID, "need nsteps >= 0 and a finite energy");
-    if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
-        return fail(SFO_E_UNSUPPORTED, "the eigenfunction run is built for 2-D and 3-D Schroedinger grids");
+    if (g->d.equation != SFO_SCHRODINGER)
+        return fail(SFO_E_UNSUPPORTED, "the eigenfunction run is built for Schroedinger grids");
     if (g->ebar_steps > 0 || g->vsteps > 0)
         return fail(SFO_E_UNSUPPORTED, "the eigenfunction run needs a time-independent potential: clear the field table");
     return g->c128 ? schro_eigen<double>(g, psi_dev, nsteps, energy, out_dev)
@@ -1745,14 +1856,32 @@ sfo_status sfo_spectrum(sfo_grid g, const double *chi_dev, int64_t nsteps, const
 sfo_status sfo_adjoint(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps, double *dL_debar_dev,
                        double *dL_dV0_dev)
 {
+    AllocCount alloc_count;
     if (!g || !psi_dev || !g_dev) return fail(SFO_E_INVALID, "null grid or state");
     if (psi_dev == g_dev) return fail(SFO_E_INVALID, "psi and g must be distinct buffers");
     sfo_status s = check_steps(g, step0, nsteps);
     if (s) return s;
     if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the Schroedinger equation");
-    if (g->vsteps > 0) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the length gauge");
+    if (g->vsteps > 0)
+        return fail(SFO_E_UNSUPPORTED, "a velocity-gauge grid: its gradient is sfo_adjoint_velocity's");
     return g->c128 ? schro_adjoint<double>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev)
                    : schro_adjoint<float>(g, psi_dev, g_dev, step0, nsteps, dL_debar_dev, dL_dV0_dev);
+}
+
+sfo_status sfo_adjoint_velocity(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
+                                double *dL_dabar_dev, double *dL_da2bar_dev, double *dL_dV0_dev)
+{
+    AllocCount alloc_count;
+    if (!g || !psi_dev || !g_dev) return fail(SFO_E_INVALID, "null grid or state");
+    if (psi_dev == g_dev) return fail(SFO_E_INVALID, "psi and g must be distinct buffers");
+    if (g->d.equation != SFO_SCHRODINGER) return fail(SFO_E_UNSUPPORTED, "the adjoint is built for the Schroedinger equation");
+    if (g->vsteps <= 0) return fail(SFO_E_STATE, "no vector-field table: set one with sfo_set_vector_field (or use sfo_adjoint)");
+    sfo_status s = check_steps(g, step0, nsteps);
+    if (s) return s;
+    return g->c128 ? schro_adjoint_velocity<double>(g, psi_dev, g_dev, step0, nsteps, dL_dabar_dev, dL_da2bar_dev,
+                                                    dL_dV0_dev)
+                   : schro_adjoint_velocity<float>(g, psi_dev, g_dev, step0, nsteps, dL_dabar_dev, dL_da2bar_dev,
+                                                   dL_dV0_dev);
 }
 
 sfo_status sfo_adjoint_noalloc(sfo_grid g, void *psi_dev, void *g_dev, int64_t step0, int64_t nsteps,
@@ -1790,7 +1919,26 @@ sfo_status sfo_norm(sfo_grid g, const void *psi_dev, double *out_host)
     double h;
     HIP_TRY(hipMemcpyAsync(&h, res, sizeof(double), hipMemcpyDeviceToHost, g->st));
     HIP_TRY(hipStreamSynchronize(g->st));
-    *out_host = h * g->dv;
+    const double nrm = h * g->dv;
+    *out_host = nrm;
+    // a NaN or Inf anywhere in the state reaches the FP64 sum (sums of |psi|^2 keep it)
+    if (!std::isfinite(nrm)) return fail(SFO_E_NUMERIC, "the state holds a non-finite value (norm %g)", nrm);
+    if (g->watch_ref > 0.0) {
+        const double drift = nrm / g->watch_ref - 1.0;
+        if (!(std::fabs(drift) <= g->watch_tol))
+            return fail(SFO_E_NUMERIC, "norm %.17g drifted by %.3e from the watched %.17g (tolerance %.3e)", nrm,
+                        drift, g->watch_ref, g->watch_tol);
+    }
+    return SFO_OK;
+}
+
+sfo_status sfo_set_norm_watch(sfo_grid g, double reference, double tolerance)
+{
+    if (!g) return fail(SFO_E_INVALID, "null grid");
+    if (!std::isfinite(reference) || reference < 0.0 || !std::isfinite(tolerance) || tolerance < 0.0)
+        return fail(SFO_E_INVALID, "need a finite reference >= 0 and a finite tolerance >= 0");
+    g->watch_ref = reference;
+    g->watch_tol = tolerance;
     return SFO_OK;
 }
 
@@ -1808,11 +1956,14 @@ sfo_status sfo_overlap(sfo_grid g, const void *a_dev, const void *b_dev, double 
     HIP_TRY(hipStreamSynchronize(g->st));
     out_host[0] = h[0] * g->dv;
     out_host[1] = h[1] * g->dv;
+    if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]))
+        return fail(SFO_E_NUMERIC, "a state holds a non-finite value (overlap %g%+gi)", out_host[0], out_host[1]);
     return SFO_OK;
 }
 
 sfo_status sfo_autotune(sfo_grid g, int32_t reps)
 {
+    AllocCount alloc_count;
     if (!g) return fail(SFO_E_INVALID, "null grid");
     if (reps < 1 || reps > 10000) return fail(SFO_E_INVALID, "reps must be in 1..10000");
     if (g->ndim == 1) return SFO_OK;  // the whole-run 1-D kernel has a single shape
@@ -1849,6 +2000,7 @@ sfo_status sfo_autotune(sfo_grid g, int32_t reps)
 
 sfo_status sfo_time_pass(sfo_grid g, int32_t kind, int32_t reps, double *avg_ms)
 {
+    AllocCount alloc_count;
     if (!g || !avg_ms) return fail(SFO_E_INVALID, "null grid or output");
     if (g->d.equation != SFO_SCHRODINGER || g->ndim < 2)
         return fail(SFO_E_UNSUPPORTED, "pass timing is for 2-D and 3-D Schroedinger grids");
@@ -1910,6 +2062,7 @@ sfo_status sfo_profile_read(sfo_grid g, int32_t kind, int64_t *count, double *to
 
 sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stream, sfo_batch *out)
 {
+    AllocCount alloc_count;
     g_err.clear();
     if (!grids || !out || count < 1) return fail(SFO_E_INVALID, "need an output handle and at least one grid");
     *out = nullptr;
@@ -1942,10 +2095,10 @@ sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stre
     if (e == hipSuccess) e = hipStreamCreate(&b->side);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc(&b->ids_d, sizeof(int) * b->ids.size());
+    if (e == hipSuccess) e = dev_malloc(&b->ids_d, sizeof(int) * b->ids.size());
     if (e == hipSuccess) e = hipMemcpy(b->ids_d, b->ids.data(), sizeof(int) * b->ids.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMalloc(&b->probs_d, (c128 ? sizeof(BatchProb<double>) : sizeof(BatchProb<float>)) * count);
+        e = dev_malloc(&b->probs_d, (c128 ? sizeof(BatchProb<double>) : sizeof(BatchProb<float>)) * count);
     if (e != hipSuccess) return guard(e);
     *out = b;
     return SFO_OK;
@@ -1968,6 +2121,7 @@ sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on)
 
 sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0, int64_t nsteps)
 {
+    AllocCount alloc_count;
     if (!b || !psi_devs) return fail(SFO_E_INVALID, "null batch or state list");
     return no_throw([&] {
         return b->c128 ? batch_run<double>(b, psi_devs, nullptr, step0, nsteps, nullptr, nullptr)
@@ -1978,6 +2132,7 @@ sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0
 sfo_status sfo_adjoint_batch(sfo_batch b, void *const *psi_devs, void *const *g_devs, int64_t step0, int64_t nsteps,
                              double *const *dL_debar_devs, double *const *dL_dV0_devs)
 {
+    AllocCount alloc_count;
     if (!b || !psi_devs || !g_devs) return fail(SFO_E_INVALID, "null batch, state list or adjoint list");
     return no_throw([&] {
         return b->c128 ? batch_run<double>(b, psi_devs, g_devs, step0, nsteps, dL_debar_devs, dL_dV0_devs)

@@ -29,10 +29,11 @@ template <typename R, int N, size_t... I> bool col_ok_n(int v, std::index_sequen
     return ok;
 }
 
-template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols)
+template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols, int ns)
 {
     if (variant < 0 || variant >= kNumColVariants) return false;
     if (ncols % kColVariants[variant].cols) return false;
+    (void)ns;
     switch (N) {
 #define CASE(n) case n: return col_ok_n<R, n>(variant, std::make_index_sequence<kNumColVariants>{});
     CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
@@ -41,8 +42,8 @@ template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols)
     }
 }
 
-template bool colpass_variant_ok<float>(int, int, int64_t);
-template bool colpass_variant_ok<double>(int, int, int64_t);
+template bool colpass_variant_ok<float>(int, int, int64_t, int);
+template bool colpass_variant_ok<double>(int, int, int64_t, int);
 
 template hipError_t launch_colpass<float>(int, int, int, const StatePtrs<float> &, int64_t, int64_t, int, int64_t,
                                           const void *const *, const KinArgs &, int, hipStream_t,

@@ -44,23 +44,34 @@ __global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT))
     constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, 256>::ROWS;
     __shared__ cx<R> lds[ROWS * Map::slots(N)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int64_t row = (int64_t)blockIdx.x * ROWS + line;
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS, row = row0 + line;
     cx<R> *sh = lds + line * Map::slots(N);
+    // addresses: the work-group's uniform base of plane q, element m (scalar
+    // registers) plus the thread's 32-bit byte offset (see row_load)
+    uint32_t lt = (uint32_t)(line * N + t) * (uint32_t)sizeof(cx<R>);
+    auto at = [&](int q, int m) {
+        char *b = scalar_base((char *)(psi + q * plane + row0 * N + m * T));
+        return (cx<R> *)(b + lt);
+    };
+    // stage factors formed from each stage's W^k, read once with the line (no
+    // table reads inside the transforms)
+    TwBase<N, RAD> wb;
+    tw_base_load(wb, tw, t);
     cx<R> v[4][RV];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[q][m] = psi[q * plane + row * N + t + m * T];
+        for (int m = 0; m < RV; ++m) v[q][m] = gload(at(q, m));
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
     if (mode & M_PHASE) {
         const double sg = (double)ph.sgn;
 #pragma unroll
         for (int m = 0; m < RV; ++m) {
             const int x = t + m * T;
             double s, c;
-            sincos_fp64(sg * ph.aV * (double)V0[row * N + x], s, c);
+            sincos_fp64(sg * ph.aV * (double)gload1(V0 + row * N + x), s, c);
             double ab = 0.0;
             if (ph.abar_a) ab += ph.ca * ph.abar_a[x];
             if (ph.abar_b) ab += ph.cb * ph.abar_b[x];
@@ -74,11 +85,13 @@ __global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT))
     }
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
+    // the offset is recomputed rather than held through the transforms
+    __asm__ __volatile__("" : "+v"(lt));
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) psi[q * plane + row * N + t + m * T] = v[q][m];
+        for (int m = 0; m < RV; ++m) gstore(at(q, m), v[q][m]);
 }
 
 template <typename R, int N, int RAD, int C>
@@ -96,14 +109,24 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
     const int64_t col = (int64_t)L * C + c;
     cx<R> *sh = lds + c;
+    // addresses: uniform base of plane q, element m (scalar registers) plus the
+    // thread's 32-bit byte offset (t nx + c) (see col_load; the launcher checks the range)
+    uint32_t tb = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(cx<R>);
+    auto at = [&](int q, int m) {
+        char *b = (char *)(psi + q * plane + (int64_t)m * T * nx + (int64_t)L * C);
+        __asm__ __volatile__("" : "+s"(b));
+        return (cx<R> *)(b + tb);
+    };
+    TwBase<N, RAD> wb;  // stage factors formed from W^k (see k_dirac_xpass)
+    tw_base_load(wb, tw, t);
     cx<R> v[4][RV];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) v[q][m] = psi[q * plane + (int64_t)(t + m * T) * nx + col];
+        for (int m = 0; m < RV; ++m) v[q][m] = gload(at(q, m));
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line<R, N, RAD, -1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
     if (mode & M_KIN) {
         const double px = kin.hbar * kin.kx[col];
         const double sg = (double)kin.sgn;
@@ -156,11 +179,12 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
     }
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line<R, N, RAD, +1, Map>(v[q], sh, t, tw);
+        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
+    __asm__ __volatile__("" : "+v"(tb));
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int m = 0; m < RV; ++m) psi[q * plane + (int64_t)(t + m * T) * nx + col] = v[q][m];
+        for (int m = 0; m < RV; ++m) gstore(at(q, m), v[q][m]);
 }
 
 // Tile shapes: radix 8 (four planes in registers), rows filling 256 threads;
@@ -195,6 +219,9 @@ static hipError_t dirac_c_n(cx<R> *psi, int nx, int64_t plane, const void *tw, c
 {
     constexpr int C = dirac_cols<R, N>();
     if (nx % C) return hipErrorInvalidValue;
+    // per-thread byte offsets within a work-group's columns are 32-bit
+    if (((int64_t)(LineShape<N, kDiracRad>::T - 1) * nx + C) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_dirac_colpass<R, N, kDiracRad, C>), dim3((unsigned)(nx / C)),
                        dim3(C * LineShape<N, kDiracRad>::T), 0, st, psi, plane, nx, (const TwEntry<R> *)tw, kin, mode);
     return hipGetLastError();

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "fft_engine.h"
+#include "sfo_validate.h"
 
 namespace sfo {
 
@@ -17,6 +18,7 @@ enum : int {
     M_FWD = 4,    // forward transform along the pass axis (last for rows, first for columns)
     M_GRAD = 16,  // adjoint partials at a step boundary (row passes with two states)
     M_CHI = 32,   // overlap with a reference k-space state after the forward transform (column passes)
+    M_VGRAD = 64, // velocity-gauge gradient partials in k-space after the forward transform (two-state k-space passes)
 };
 
 // The states a pass transforms together: p[0] alone, or the state p[0] and
@@ -58,6 +60,13 @@ struct KinArgs {
     int sgn;
     const void *chi_ref = nullptr;
     double *chi_part = nullptr;
+    // M_VGRAD (two states psi~, g~ in k-space): wave numbers of the line's
+    // other axes, kvA[col % nA] and kvB[col / nA] (kvB null: 0), and along the
+    // line, kvL[e]; vpart[4 slot + {0, 1, 2, 3}] = sum over the work-group's
+    // points of (kA, kB, kL, 1) Im(conj(g~) psi~), slot = the work-group's
+    // linear index
+    const double *kvA = nullptr, *kvB = nullptr, *kvL = nullptr;
+    double *vpart = nullptr;
 };
 
 // Dirac real-space factor of a row pass (4 planes):
@@ -83,13 +92,28 @@ struct DiracKinArgs {
 
 // 1-D whole-run kernel arguments (one work-group per problem).
 struct Run1DArgs {
-    const double2 *kin;  // N kinetic factors (1/N folded in)
+    const double2 *kin;  // N kinetic factors (1/N folded in); step st uses kin + st * kin_stride
     const double *ebar;  // per-step field integrals (1 per step) or null
     int64_t step0, nsteps;
     double aV_half;   // tau / (2 hbar)
     double inv_2hbar; // 1 / (2 hbar)
     double xmin, dx;
     int dir;          // +1 forward steps, -1 inverse steps (last first)
+    int64_t kin_stride = 0;  // velocity gauge: per-step kinetic tables, N apart (0: one table)
+    // velocity-gauge reverse sweep: wave numbers of the line (kv) and, per
+    // step s of the run, vmom[4 s + {2, 3}] = sum_k (k, 1) Im(conj(g~) psi~)
+    // in k-space after the forward transforms ({0, 1} are set to 0)
+    const double *kv = nullptr;
+    double *vmom = nullptr;
+    // eigenstate runs (time-independent potential, dir = +1): chi[2 s + {0, 1}]
+    // = dv sum conj(psi_0) psi_s with ref (a state-sized buffer) keeping
+    // P psi_0; or the windowed eigenfunction, accumulated in FP64 in eig_acc
+    // and written to eig_out (see run1d_tile)
+    double *chi = nullptr;
+    void *ref = nullptr;
+    double2 *eig_acc = nullptr;
+    void *eig_out = nullptr;
+    double eig_E = 0.0, tau = 0.0, hbar = 1.0, dv = 1.0;
 };
 
 // One problem of a batch (device memory).  A grouped launch covers every
@@ -130,17 +154,32 @@ struct RowVariant {
     int rad, threads, wpe;
     bool pad;   // padded LDS map with immediate offsets (else the XOR swizzle)
     bool late;  // potential loaded after the inverse transform (fewer registers held)
+    bool pre = false;  // complex128: stage factors formed from each stage's W^k, read with the line
 };
 struct ColVariant {
     int rad, cols, wpe;
+    int pipe = 0;        // > 0: a forward step's k-space pass walks this many column groups per work-group,
+                         // the next group's loads in flight while the current one transforms (k_colpipe)
+    int order = 0;       // k_colpipe: where the prefetch is issued (0: group start, 1: after the forward transform)
+    bool pre = false;    // stage factors formed from each stage's W^k, read once per work-group (no table per stage)
 };
 constexpr RowVariant kRowVariants[] = {
     {16, 256, 1, true, false}, {16, 128, 1, true, false}, {16, 512, 1, true, false}, {16, 256, 3, true, false},
     {16, 256, 4, true, false}, {8, 256, 1, false, false},  {8, 512, 1, false, false},  {8, 256, 4, false, false},
     {8, 256, 1, true, false},  {8, 512, 1, true, false},  {16, 256, 4, true, true},  {16, 128, 4, true, true},
-    {16, 256, 1, true, true},  {8, 256, 1, false, true}};
-constexpr ColVariant kColVariants[] = {{16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2},
-                                       {16, 2, 4}, {8, 8, 1},  {8, 4, 1},  {8, 2, 4}};
+    {16, 256, 1, true, true},  {8, 256, 1, false, true},
+    // complex128 with the stage factors formed from W^k (for complex64 these equal shapes 0, 11, 12 and 13)
+    {16, 256, 1, true, false, true}, {16, 128, 4, true, true, true}, {16, 256, 1, true, true, true},
+    {8, 256, 1, false, true, true}};
+constexpr ColVariant kColVariants[] = {
+    {16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2}, {16, 2, 4}, {8, 8, 1}, {8, 4, 1}, {8, 2, 4},
+    // pipelined k-space pass: 2, 4 or 8 column groups per work-group, prefetch at the group start (order 0)
+    // or after the forward transform (order 1)
+    {16, 4, 2, 2, 0}, {16, 4, 2, 2, 1}, {16, 4, 2, 4, 0}, {16, 4, 2, 4, 1},
+    {16, 2, 2, 4, 0}, {16, 2, 2, 4, 1}, {16, 2, 2, 8, 0}, {16, 2, 2, 8, 1},
+    // plain shapes with the stage factors formed from W^k
+    {16, 8, 1, 0, 0, true}, {16, 4, 1, 0, 0, true}, {16, 4, 2, 0, 0, true}, {16, 2, 1, 0, 0, true},
+    {16, 2, 4, 0, 0, true}};
 constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);
 constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 
@@ -171,6 +210,14 @@ hipError_t launch_1d_adjoint(int N, cx<R> *psi, cx<R> *gv, const void *V0, const
 hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int ndim, double scale, double *out,
                             hipStream_t st);
 
+// Velocity-gauge gradient from the k-space partials of the reverse sweep
+// (4 per slot and step, see KinArgs): for step j < nsteps and axis a < ndim,
+// dA[j ndim + a] = sA * sum_slots part[(j nslots + slot) 4 + idx(a)] with
+// idx = {2} (1-D), {0, 2} (2-D), {0, 1, 2} (3-D), and
+// dA2[j] = sA2 * sum_slots part[(j nslots + slot) 4 + 3]; slot order.
+hipError_t launch_vgrad_sum(const double *part, int nslots, int64_t nsteps, int ndim, double sA, double sA2,
+                            double *dA, double *dA2, hipStream_t st);
+
 // chi[2 j + {0, 1}] = scale * sum over the nslots partials of step j, in slot
 // order (deterministic), j < nsteps.
 hipError_t launch_chi_sum(const double *part, int nslots, int64_t nsteps, double scale, double *chi, hipStream_t st);
@@ -193,11 +240,16 @@ void line_stages(int N, int RAD, int *radix, int *span, int *nst);
 // Whether a variant exists for this line length and precision (and, for
 // columns, divides the number of lines).
 template <typename R> bool xpass_variant_ok(int variant, int N);
-template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols);
+template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols, int ns = 1);
 
 template <typename R>
 hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const void *V0,
                      const void *tw, const Run1DArgs &a, hipStream_t st, const GroupArgs<R> &grp = GroupArgs<R>{});
+
+// One 1-D line's eigenstate run (a.chi: autocorrelation; a.eig_acc: windowed
+// eigenfunction), dir = +1, no field table.
+template <typename R>
+hipError_t launch_1d_eigen(int N, cx<R> *psi, const void *V0, const void *tw, const Run1DArgs &a, hipStream_t st);
 
 template <typename R>
 hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
@@ -236,10 +288,5 @@ hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t
 hipError_t launch_absmax(const double *src, int64_t n, double *partials, double *out, hipStream_t st);
 
 constexpr int kReduceBlocks = 1024;
-
-// Maximum line length of the row/column passes and of the 1-D kernel.
-constexpr int kMaxPassN = 4096;
-constexpr int kMax1DN = 8192;
-constexpr int kMinN = 64;
 
 }  // namespace sfo

@@ -43,6 +43,17 @@ __global__ void __launch_bounds__((LineShape<N, RAD>::T))
                               sh, threadIdx.x);
 }
 
+// 1-D eigenstate run of one line: MODE 1 autocorrelation, MODE 2 windowed
+// eigenfunction (see run1d_tile).
+template <typename R, typename VT, int N, int RAD, int MODE>
+__global__ void __launch_bounds__((LineShape<N, RAD>::T))
+    k_1d_eigen(cx<R> *__restrict__ psi, const VT *__restrict__ V0, const TwEntry<R> *__restrict__ tw, Run1DArgs a)
+{
+    __shared__ cx<R> sh[RowMap<R, RAD>::slots(N)];
+    __shared__ double red[16][3];
+    run1d_tile<R, VT, N, RAD, MODE>(psi, V0, tw, a, sh, threadIdx.x, red);
+}
+
 // ------------------------------------------------------------ 1-D adjoint --
 template <typename R, typename VT, int N, int RAD>
 __global__ void __launch_bounds__((LineShape<N, RAD>::T))
@@ -73,6 +84,27 @@ __global__ void k_ebar_grad(const double *part, int nslots, int64_t nsteps, int 
             m0 += part[(s * nslots + k) * 3 + a];
         }
         out[i] = (m1 + m0) * scale;
+    }
+}
+
+// Velocity-gauge gradient: per step j and axis a (one thread each; the
+// step's A2bar derivative by the thread of axis 0), the slots summed in slot
+// order (see launch_vgrad_sum).
+__global__ void k_vgrad_sum(const double *part, int nslots, int64_t nsteps, int ndim, double sA, double sA2, double *dA,
+                            double *dA2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps * ndim; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i / ndim;
+        const int a = (int)(i % ndim);
+        // partial index of axis a: the moment along the line is entry 2
+        const int idx = a == ndim - 1 ? 2 : a;
+        double m = 0.0, m1 = 0.0;
+        for (int k = 0; k < nslots; ++k) {
+            m += part[(j * nslots + k) * 4 + idx];
+            m1 += part[(j * nslots + k) * 4 + 3];
+        }
+        if (dA) dA[i] = m * sA;
+        if (dA2 && a == 0) dA2[j] = m1 * sA2;
     }
 }
 
@@ -292,6 +324,30 @@ hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const vo
 }
 
 template <typename R, typename VT, int N>
+static hipError_t eig1d_n(cx<R> *psi, const void *V0, const void *tw, const Run1DArgs &a, hipStream_t st)
+{
+    constexpr int threads = LineShape<N, kRad>::T;
+    if (a.chi)
+        hipLaunchKernelGGL((k_1d_eigen<R, VT, N, kRad, 1>), dim3(1), dim3(threads), 0, st, psi, (const VT *)V0,
+                           (const TwEntry<R> *)tw, a);
+    else
+        hipLaunchKernelGGL((k_1d_eigen<R, VT, N, kRad, 2>), dim3(1), dim3(threads), 0, st, psi, (const VT *)V0,
+                           (const TwEntry<R> *)tw, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_1d_eigen(int N, cx<R> *psi, const void *V0, const void *tw, const Run1DArgs &a, hipStream_t st)
+{
+    using VT = typename std::conditional<sizeof(R) == 4, float, double>::type;
+    if ((!a.chi && !a.eig_acc) || (a.chi && !a.ref) || (a.eig_acc && !a.eig_out) || a.dir != 1 || a.ebar)
+        return hipErrorInvalidValue;
+#define CALL(n) eig1d_n<R, VT, n>(psi, V0, tw, a, st)
+    SFO_SWITCH_1D_N(N, CALL)
+#undef CALL
+}
+
+template <typename R, typename VT, int N>
 static hipError_t adj1d_n(cx<R> *psi, cx<R> *gv, const void *V0, const void *tw, const Run1DArgs &a, double wbase,
                           double *acc, double *mom, hipStream_t st, const GroupArgs<R> &grp, int ngroup)
 {
@@ -319,6 +375,16 @@ hipError_t launch_ebar_grad(const double *part, int nslots, int64_t nsteps, int 
     const int64_t n = nsteps * ndim;
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_ebar_grad, dim3(blocks), dim3(256), 0, st, part, nslots, nsteps, ndim, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vgrad_sum(const double *part, int nslots, int64_t nsteps, int ndim, double sA, double sA2,
+                            double *dA, double *dA2, hipStream_t st)
+{
+    if (nsteps <= 0 || (!dA && !dA2)) return hipSuccess;
+    const int64_t n = nsteps * ndim;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_vgrad_sum, dim3(blocks), dim3(256), 0, st, part, nslots, nsteps, ndim, sA, sA2, dA, dA2);
     return hipGetLastError();
 }
 
@@ -386,6 +452,10 @@ hipError_t launch_convert_v0(const double *src, void *dst, bool to_fp64, int64_t
     return hipGetLastError();
 }
 
+template hipError_t launch_1d_eigen<float>(int, cx<float> *, const void *, const void *, const Run1DArgs &,
+                                           hipStream_t);
+template hipError_t launch_1d_eigen<double>(int, cx<double> *, const void *, const void *, const Run1DArgs &,
+                                            hipStream_t);
 template hipError_t launch_1d<float>(int, cx<float> *, int, int64_t, const void *, const void *, const Run1DArgs &,
                                      hipStream_t, const GroupArgs<float> &);
 template hipError_t launch_1d<double>(int, cx<double> *, int, int64_t, const void *, const void *, const Run1DArgs &,

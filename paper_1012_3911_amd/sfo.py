@@ -16,13 +16,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfo.so")
 
-SFO_OK, SFO_E_INVALID, SFO_E_UNSUPPORTED, SFO_E_NOMEM, SFO_E_HIP, SFO_E_STATE = 0, -1, -2, -3, -4, -5
+SFO_OK, SFO_E_INVALID, SFO_E_UNSUPPORTED, SFO_E_NOMEM, SFO_E_HIP, SFO_E_STATE, SFO_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 SCHRODINGER, DIRAC = 0, 1
 C64, C128 = 0, 1
 UNFUSED = 1 << 1
 
 _STATUS_NAMES = {0: "SFO_OK", -1: "SFO_E_INVALID", -2: "SFO_E_UNSUPPORTED", -3: "SFO_E_NOMEM",
-                 -4: "SFO_E_HIP", -5: "SFO_E_STATE"}
+                 -4: "SFO_E_HIP", -5: "SFO_E_STATE", -6: "SFO_E_NUMERIC"}
 
 
 class SfoError(RuntimeError):
@@ -55,7 +55,7 @@ EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
            "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
            "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
-           "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_adjoint_noalloc", "sfo_last_error",
+           "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_adjoint_noalloc", "sfo_set_norm_watch", "sfo_adjoint_velocity", "sfo_last_error",
            "sfo_version"]
 
 KERNEL_ROW, KERNEL_COLUMN, KERNEL_ZCOLUMN, KERNEL_LINE1D = 0, 1, 2, 3
@@ -81,7 +81,9 @@ def load_library(path: str = LIB_PATH):
         "sfo_propagate": [P, P, I64, I64],
         "sfo_adjoint": [P, P, P, I64, I64, P, P],
         "sfo_adjoint_noalloc": [P, P, P, I64, I64, P, P],
+        "sfo_adjoint_velocity": [P, P, P, I64, I64, P, P, P],
         "sfo_norm": [P, P, P],
+        "sfo_set_norm_watch": [P, ctypes.c_double, ctypes.c_double],
         "sfo_overlap": [P, P, P, P],
         "sfo_fft": [P, P, I32],
         "sfo_autotune": [P, I32],
@@ -269,6 +271,19 @@ class Grid:
                                 ctypes.c_void_p(dv.data_ptr()) if dv is not None else None), "sfo_adjoint")
         return de, dv
 
+    def adjoint_velocity(self, psi, g, step0: int, nsteps: int, want_dV0: bool = True):
+        """Reverse sweep of a velocity-gauge run: returns (dL/dAbar (nsteps, ndim), dL/dA2bar (nsteps,),
+        dL/dV0 or None) as FP64 CUDA tensors."""
+        torch = _torch()
+        da = torch.zeros((nsteps, self.ndim), dtype=torch.float64, device="cuda")
+        da2 = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+        dv = torch.zeros(self.n[::-1], dtype=torch.float64, device="cuda") if want_dV0 else None
+        _check(_lib.sfo_adjoint_velocity(self._h, self._state(psi), self._state(g, "g"), int(step0), int(nsteps),
+                                         ctypes.c_void_p(da.data_ptr()), ctypes.c_void_p(da2.data_ptr()),
+                                         ctypes.c_void_p(dv.data_ptr()) if dv is not None else None),
+               "sfo_adjoint_velocity")
+        return da, da2, dv
+
     def adjoint_noalloc(self, psi, g, step0: int, nsteps: int, de, dv=None):
         """sfo_adjoint_noalloc into caller-allocated outputs de (nsteps x ndim FP64) and dv (N points FP64 or None)."""
         _check(_lib.sfo_adjoint_noalloc(self._h, self._state(psi), self._state(g, "g"), int(step0), int(nsteps),
@@ -276,6 +291,10 @@ class Grid:
                                         ctypes.c_void_p(dv.data_ptr()) if dv is not None else None),
                "sfo_adjoint_noalloc")
         return de, dv
+
+    def set_norm_watch(self, reference: float, tolerance: float):
+        """sfo_norm then raises (SFO_E_NUMERIC) once |norm/reference - 1| > tolerance; reference 0 = off."""
+        _check(_lib.sfo_set_norm_watch(self._h, float(reference), float(tolerance)), "sfo_set_norm_watch")
 
     def norm(self, psi) -> float:
         out = ctypes.c_double()

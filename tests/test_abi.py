@@ -92,4 +92,6 @@ def test_null_arguments(lib):
     assert lib.sfo_eigenfunction(None, None, 4, ctypes.c_double(0.0), None) == -1
     assert lib.sfo_set_vector_field(None, None, None, 4) == -1
     assert lib.sfo_adjoint_noalloc(None, None, None, 0, 1, None, None) == -1
+    assert lib.sfo_set_norm_watch(None, 1.0, 1e-6) == -1
+    assert lib.sfo_adjoint_velocity(None, None, None, 0, 1, None, None, None) == -1
     assert lib.sfo_version().decode().startswith("sfo")

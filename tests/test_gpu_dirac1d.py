@@ -24,9 +24,9 @@ def _wl(N, S, dt=2e-4, L=10.0, A0=30.0):
     return wl
 
 
-@pytest.mark.parametrize("dtype,N,S,tol", [("c128", 1024, 200, 1e-11), ("c64", 1024, 200, 1e-5),
-                                           ("c128", 64, 50, 1e-11), ("c128", 8192, 20, 1e-11),
-                                           ("c128", 4096, 20, 1e-11)])
+@pytest.mark.parametrize("dtype,N,S,tol", [("c128", 1024, 200, 1e-12), ("c64", 1024, 200, 1e-5),
+                                           ("c128", 64, 50, 1e-12), ("c128", 8192, 20, 1e-12),
+                                           ("c128", 4096, 20, 1e-12)])
 def test_dirac1d_matches_oracle(dtype, N, S, tol):
     import torch
 
@@ -37,7 +37,9 @@ def test_dirac1d_matches_oracle(dtype, N, S, tol):
     torch.cuda.synchronize()
     p0 = wl.psi0.astype(np.complex64).astype(complex) if dtype == "c64" else wl.psi0
     ref = orc.dirac1d(p0, (N,), wl.xmin, wl.xmax, wl.dt, wl.V0, wl.abar_y, nsteps=S, c=C)
-    assert rel_l2(psi.cpu().numpy(), ref) < tol
+    err = rel_l2(psi.cpu().numpy(), ref)
+    print("dirac1d %s N=%d %d steps: rel L2 vs oracle %.3e" % (dtype, N, S, err), flush=True)
+    assert err < tol
     if dtype == "c128":
         assert abs(g.norm(psi) / g.norm(to_device(wl.psi0, dtype)) - 1) < 1e-12
     g.close()
@@ -54,7 +56,7 @@ def test_dirac1d_steps_from_an_offset():
     g.propagate(psi, 30, 30)
     torch.cuda.synchronize()
     ref = orc.dirac1d(wl.psi0, (512,), wl.xmin, wl.xmax, wl.dt, wl.V0, wl.abar_y, step0=30, nsteps=30, c=C)
-    assert rel_l2(psi.cpu().numpy(), ref) < 1e-11
+    assert rel_l2(psi.cpu().numpy(), ref) < 1e-12
     g.close()
 
 

@@ -133,9 +133,20 @@ def test_every_tile_shape(orc, dtype):
     tol = C128_TOL if dtype == "c128" else C64_TOL
     g = make_grid(wl, dtype)
     base = g.plan
+
+    def sweep():
+        # the reverse sweep with the forced shapes (a single-state column shape with
+        # line pairs hands the two-state passes its plain equivalent)
+        psi = to_device(ref, dtype)
+        gv = to_device(wl.psi0, dtype)
+        dE, dV = g.adjoint(psi, gv, 0, wl.nsteps)
+        torch.cuda.synchronize()
+        return dE.cpu().numpy(), dV.cpu().numpy()
+
+    dE0, dV0 = sweep()
     tried = 0
     for kind in (0, 1):
-        for v in range(16):
+        for v in range(32):
             p = list(base)
             p[kind] = v
             try:
@@ -147,8 +158,12 @@ def test_every_tile_shape(orc, dtype):
             torch.cuda.synchronize()
             err = rel_l2(psi.cpu().numpy(), ref)
             assert err < tol, (kind, v, err)
+            dE, dV = sweep()
+            gtol = 1e-12 if dtype == "c128" else 1e-4
+            assert np.linalg.norm(dE - dE0) <= gtol * np.linalg.norm(dE0), (kind, v)
+            assert np.linalg.norm(dV - dV0) <= gtol * np.linalg.norm(dV0), (kind, v)
             tried += 1
-    assert tried >= 8
+    assert tried >= 16
     g.plan = base
     chosen = g.autotune(3)
     psi = to_device(wl.psi0, dtype)

@@ -28,7 +28,8 @@ def _setup(n, L, dt, S, A0=0.6, w=0.7, pol=(1.0, 0.5, -0.3)):
 
 
 @pytest.mark.parametrize("dtype,n,S,tol", [("c128", (128, 64), 60, 1e-12), ("c64", (128, 64), 60, 1e-5),
-                                           ("c128", (64, 64, 64), 12, 1e-12)])
+                                           ("c128", (64, 64, 64), 12, 1e-12), ("c128", (1024,), 200, 1e-12),
+                                           ("c64", (1024,), 200, 1e-5), ("c128", (8192,), 40, 1e-12)])
 def test_velocity_gauge_matches_oracle(dtype, n, S, tol):
     import torch
 
@@ -40,7 +41,25 @@ def test_velocity_gauge_matches_oracle(dtype, n, S, tol):
     torch.cuda.synchronize()
     p0 = wl.psi0.astype(np.complex64).astype(complex) if dtype == "c64" else wl.psi0
     ref = orc.schrodinger_velocity(p0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, abar, a2bar, nsteps=S)
-    assert rel_l2(psi.cpu().numpy(), ref) < tol
+    err = rel_l2(psi.cpu().numpy(), ref)
+    print("velocity gauge %s %s %d steps: rel L2 vs oracle %.3e" % (dtype, n, S, err), flush=True)
+    assert err < tol
+    g.close()
+
+
+def test_velocity_gauge_1d_from_an_offset_and_reversed():
+    """1-D whole-run kernel with per-step kinetic tables: steps 20..59 of the table
+    against the oracle, then the exact inverse run back to the start (complex128)."""
+    import torch
+
+    wl, abar, a2bar = _setup((512,), 8.0, 0.05, 60)
+    g = make_grid(wl, "c128")
+    g.set_vector_field(abar, a2bar)
+    psi = to_device(wl.psi0, "c128")
+    g.propagate(psi, 20, 40)
+    torch.cuda.synchronize()
+    ref = orc.schrodinger_velocity(wl.psi0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, abar, a2bar, step0=20, nsteps=40)
+    assert rel_l2(psi.cpu().numpy(), ref) < 1e-12
     g.close()
 
 
@@ -80,7 +99,7 @@ def test_velocity_gauge_rejects():
     with pytest.raises(sfo.SfoError):
         g.propagate(psi, 2, 4)  # beyond the table
     with pytest.raises(sfo.SfoError):
-        g.adjoint(psi, to_device(wl.psi0, "c128"), 0, 4)
+        g.adjoint(psi, to_device(wl.psi0, "c128"), 0, 4)  # its gradient is sfo_adjoint_velocity's
     with pytest.raises(sfo.SfoError):
         g.autocorrelation(psi, 4)
     g.set_field(None)  # releases the velocity tables: no field at all
@@ -88,6 +107,84 @@ def test_velocity_gauge_rejects():
     g.close()
     w1 = W.Workload("l", "schrodinger", (256,), (-5.0,), (5.0,), 0.01, 1, np.zeros(256), np.ones(256, complex))
     g1 = make_grid(w1, "c128")
+    with pytest.raises(ValueError):
+        g1.set_vector_field(np.zeros((4, 2)), np.zeros(4))  # a 2-D table for a 1-D grid
     with pytest.raises(sfo.SfoError):
-        g1.set_vector_field(np.zeros((4, 1)), np.zeros(4))
+        g1.set_vector_field(np.full((4, 1), np.nan), np.zeros(4))
     g1.close()
+
+
+# ------------------------------------------------------------ reverse sweep --
+
+def _vg_adjoint_case(n, S, seed):
+    wl, abar, a2bar = _setup(n, 8.0, 0.05, S)
+    rng = np.random.default_rng(seed)
+    abar = abar + 0.02 * rng.uniform(-1, 1, size=abar.shape)  # a control with structure on every axis
+    axes = [-8.0 + 16.0 / m * np.arange(m) for m in n]
+    X = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+    target = np.exp(-((X[0] - 0.5) ** 2 + sum(x ** 2 for x in X[1:])) / 2 + 0.2j * X[0]).astype(complex)
+    return wl, abar, a2bar, target
+
+
+@pytest.mark.parametrize("dtype,n,S", [("c128", (512,), 80), ("c64", (512,), 80), ("c128", (128, 64), 40),
+                                       ("c64", (128, 64), 40), ("c128", (64, 64, 64), 8), ("c128", (2048,), 30)])
+def test_velocity_adjoint_matches_oracle(dtype, n, S):
+    """sfo_adjoint_velocity (k-space gradient partials inside the reverse
+    sweep) against the oracle's stored-trajectory gradient, the derivative of
+    each step written out in real space: dL/dAbar, dL/dA2bar (loss
+    Re<target|psi_T>, which sees the global phase), dL/dV0, psi(0) and g(0)."""
+    import torch
+
+    wl, abar, a2bar, target = _vg_adjoint_case(n, S, seed=len(n) + S)
+    psiT = orc.schrodinger_velocity(wl.psi0, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, abar, a2bar, nsteps=S)
+    gT = wl.dv * target
+    g0, da, da2, dV = orc.schrodinger_velocity_adjoint(wl.psi0, gT, wl.n, wl.xmin, wl.xmax, wl.dt, wl.V0, abar,
+                                                       a2bar, nsteps=S)
+    g = make_grid(wl, dtype)
+    g.set_vector_field(abar, a2bar)
+    p0 = psiT.astype(np.complex64).astype(complex) if dtype == "c64" else psiT
+    psi = to_device(p0, dtype)
+    gv = to_device(gT, dtype)
+    gda, gda2, gdV = g.adjoint_velocity(psi, gv, 0, S)
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    errs = (rel(psi.cpu().numpy(), wl.psi0), rel(gv.cpu().numpy(), g0), rel(gda.cpu().numpy(), da),
+            rel(gda2.cpu().numpy(), da2), rel(gdV.cpu().numpy(), dV))
+    print("velocity adjoint %s %s %d steps: psi0 %.2e g0 %.2e dAbar %.2e dA2bar %.2e dV0 %.2e" % ((dtype, n, S) + errs),
+          flush=True)
+    tol = 1e-11 if dtype == "c128" else 1e-4
+    assert errs[0] < (1e-12 if dtype == "c128" else 1e-5)
+    assert max(errs[1:]) < tol, errs
+    g.close()
+
+
+def test_velocity_adjoint_central_differences_gpu():
+    """dL/dAbar of |<target|psi_T>|^2 from the GPU reverse sweep against central
+    differences of GPU forward runs (complex128, 2-D, autotuned shapes)."""
+    import torch
+
+    n, S = (128, 64), 20
+    wl, abar, a2bar, target = _vg_adjoint_case(n, S, seed=9)
+    g = make_grid(wl, "c128")
+    g.autotune(2)
+
+    def forward(ab):
+        g.set_vector_field(ab, a2bar)
+        psi = to_device(wl.psi0, "c128")
+        g.propagate(psi, 0, S)
+        torch.cuda.synchronize()
+        ov = wl.dv * np.vdot(target, psi.cpu().numpy())
+        return abs(ov) ** 2, psi, ov
+
+    _, psi, ov = forward(abar)
+    gv = to_device(2 * ov * target * wl.dv, "c128")
+    gda, _, _ = g.adjoint_velocity(psi, gv, 0, S, want_dV0=False)
+    gda = gda.cpu().numpy()
+    h = 1e-5
+    for j, a in ((0, 0), (7, 1), (13, 0), (19, 1)):
+        ap, am = abar.copy(), abar.copy()
+        ap[j, a] += h
+        am[j, a] -= h
+        fd = (forward(ap)[0] - forward(am)[0]) / (2 * h)
+        assert abs(fd - gda[j, a]) <= 1e-4 * max(abs(fd), 1e-3 * np.abs(gda).max()), (j, a, fd, gda[j, a])
+    g.close()
