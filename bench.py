@@ -10,13 +10,13 @@ Seeded synthetic inputs (no dataset), state resident in HBM.
 A "step" is one Strang step of the whole grid: the row pass (inverse
 x-transform, merged potential factor, forward x-transform) and the column
 pass (forward y-transform, kinetic factor, inverse y-transform).  `value` is
-the complex64 path (FP32 storage and butterflies, FP64 phases and
-reductions); the complex128 path, fused and in the paper's unfused
-five-launch form, is reported beside it, and so are the forward run plus
-reverse sweep (adjoint) of the same workload and the 64-problem batched
-control workload (forward, and forward + reverse sweep).  As an external
-point of comparison only, the same steps written with torch.fft (the vendor
-hipFFT/rocFFT) and torch elementwise products are timed too.
+the complex128 path, the paper's precision (FP64 storage, butterflies,
+phases and reductions); the complex64 path (FP32 storage and butterflies,
+FP64 phases and reductions) and the paper's unfused five-launch complex128
+step are reported beside it under `paths`, each fused path with its own
+roofline block, and so are the forward run plus reverse sweep (adjoint) of
+the same workload and the 64-problem batched control workload (forward,
+and forward + reverse sweep).
 
 Roofline: the dominant pass's algorithmic bytes per launch divided by its
 average launch duration within steps of the propagation's pass sequence,
@@ -44,29 +44,51 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
-# HBM bytes per launch of the 2048 x 2048 complex64 passes, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
-# counters read for a plain 512 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE
-# x 1); keyed by pass and tile-shape number.  Valid only for the kernel
+# HBM bytes per launch of the 2048 x 2048 passes, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
+# plain 512 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1); keyed by
+# precision, then pass and tile-shape number.  Valid only for the kernel
 # sources they were taken on: a different fingerprint reports null.
-TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h", "sfo_impl.h", "sfo_row.hip", "sfo_col.hip"]
+# the kernels' code and their tile-shape table (the dispatch files only choose among them)
+TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h"]
+TRAFFIC_TABLE = ("sfo_impl.h", b"struct RowVariant {", b"constexpr int kNumColVariants")
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "ea3ade385d665e590b417e4c5b8556b42414e1e817cefa9ced1ae200f88da2b6",
-    # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read
-    "row/0": (24724, 32768), "row/1": (24726, 32768), "row/2": (24719, 32768), "row/3": (24726, 32768),
-    "row/4": (24722, 32768), "row/5": (24703, 32768), "row/6": (24702, 32768), "row/7": (24694, 32768),
-    "row/8": (24687, 32768), "row/9": (24687, 32768), "row/10": (24726, 32768), "row/11": (24725, 32768),
-    "row/12": (24721, 32768), "row/13": (24702, 32768),
-    "column/0": (16663, 32831), "column/1": (16659, 32777), "column/2": (16660, 33253),
-    "column/4": (16650, 32778), "column/5": (16660, 33420), "column/7": (16767, 32830),
-    "column/8": (16631, 36339),
+    "sources_sha256": "85f803e8a983abcec36085aecc158dddf52f29fa6710fac36c09978b29fe322c",
+    # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read; the pipelined
+    # column shapes that differ only in groups per work-group share one kernel and one entry
+    "c64": {
+        "row/0": (24718, 32768), "row/1": (24718, 32768), "row/2": (24717, 32768), "row/3": (24720, 32768),
+        "row/4": (24726, 32768), "row/5": (24703, 32768), "row/6": (24698, 32768), "row/7": (24702, 32768),
+        "row/8": (24690, 32768), "row/9": (24684, 32768), "row/10": (24723, 32768), "row/11": (24725, 32768),
+        "row/12": (24723, 32768), "row/13": (24702, 32768), "row/14": (24718, 32768), "row/15": (24725, 32768),
+        "row/16": (24723, 32768), "row/17": (24702, 32768), "column/0": (16661, 32831), "column/1": (16658, 32779),
+        "column/2": (16658, 33194), "column/4": (16656, 32786), "column/5": (16660, 33223),
+        "column/7": (16770, 32796), "column/8": (16635, 33845), "column/9": (16814, 32768),
+        "column/10": (16798, 32768), "column/11": (16814, 32768), "column/12": (16798, 32768),
+        "column/13": (16848, 32768), "column/14": (16850, 32768), "column/15": (16848, 32768),
+        "column/16": (16850, 32768), "column/17": (16660, 33221), "column/18": (16657, 33020),
+        "column/19": (16652, 33042), "column/20": (16659, 33386), "column/21": (16659, 33567),
+    },
+    "c128": {
+        "row/0": (49594, 65536), "row/1": (49431, 65536), "row/2": (49561, 65536), "row/3": (49621, 65536),
+        "row/4": (49607, 65536), "row/5": (49393, 65536), "row/6": (49457, 65536), "row/7": (49393, 65536),
+        "row/8": (49383, 65536), "row/9": (49452, 65536), "row/10": (49576, 65536), "row/11": (49434, 65536),
+        "row/12": (49616, 65536), "row/13": (49388, 65536), "row/14": (49330, 65536), "row/15": (49330, 65536),
+        "row/16": (49331, 65536), "row/17": (50068, 72752), "column/1": (33468, 75018), "column/2": (33986, 90799),
+        "column/4": (33457, 76838), "column/5": (34174, 91712), "column/7": (33373, 65706),
+        "column/8": (33373, 87253), "column/9": (41697, 86355), "column/10": (33377, 67984),
+        "column/11": (41697, 86355), "column/12": (33377, 67984), "column/13": (40642, 89698),
+        "column/14": (33435, 66256), "column/15": (40642, 89698), "column/16": (33435, 66256),
+        "column/18": (33187, 65752), "column/19": (33188, 65862), "column/20": (33330, 79812),
+        "column/21": (33318, 79655),
+    },
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
 
 
-def measured_traffic(kind, variant):
-    v = MEASURED_TRAFFIC.get("%s/%d" % (kind, variant))
+def measured_traffic(dtype, kind, variant):
+    v = MEASURED_TRAFFIC.get(dtype, {}).get("%s/%d" % (kind, variant))
     if v is None:
         return None
     return (FETCH_SCALE * v[0] + WRITE_SCALE * v[1]) * _KIB
@@ -76,9 +98,14 @@ def sources_fingerprint():
     import hashlib
 
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1012_3911_amd", "csrc")
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1012_3911_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    f, first, last = TRAFFIC_TABLE
+    with open(os.path.join(csrc, f), "rb") as fh:
+        t = fh.read()
+    h.update(t[t.index(first):t.index(last)])
     return h.hexdigest()
 
 
@@ -136,16 +163,18 @@ def bench_path(wl, dtype, flags, steps, warmup):
     # back launches of one pass (which finds its own output partly in cache);
     # and the timed sequence again with an event pair around every launch
     # (which adds the dispatch gap to each)
-    kinds = (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))
-    kern = {name: g.time_pass(kind, 200, in_step=True) for name, kind in kinds}
-    kern_b2b = {name: g.time_pass(kind, 200) for name, kind in kinds}
-    g.profile(True)
-    run_steps(g, psi, min(steps, 2 * wl.nsteps), wl.nsteps)
-    kern_ev = {name: g.profile_read(kind) for name, kind in
-               (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))}
-    g.profile(False)
+    # (fused paths only: the unfused step launches other kernels)
+    kern = kern_b2b = kern_ev = None
+    if not flags:
+        kinds = (("row", sfo.KERNEL_ROW), ("column", sfo.KERNEL_COLUMN))
+        kern = {name: g.time_pass(kind, 200, in_step=True) for name, kind in kinds}
+        kern_b2b = {name: g.time_pass(kind, 200) for name, kind in kinds}
+        g.profile(True)
+        run_steps(g, psi, min(steps, 2 * wl.nsteps), wl.nsteps)
+        kern_ev = {name: g.profile_read(kind) for name, kind in kinds}
+        g.profile(False)
     fa = None
-    if dtype == "c64" and not flags:
+    if not flags:
         # forward run + reverse sweep (state, adjoint and both gradients) of the same workload
         gT = (0.5 * psi).contiguous()
         g.propagate(psi, 0, wl.nsteps)
@@ -222,7 +251,7 @@ def bench_config(wl, dtype, runs=2):
         g.set_vector_potential(wl.abar_y)
     else:
         g.set_field(wl.ebar)
-    plan = list(g.autotune(5)) if (wl.equation == "schrodinger" and wl.ndim >= 2) else None
+    plan = list(g.autotune(5)) if wl.ndim >= 2 else None
     tdt = torch.complex64 if dtype == "c64" else torch.complex128
     psi = torch.from_numpy(wl.psi0).to("cuda").to(tdt).contiguous()
     g.propagate(psi, 0, min(wl.nsteps, 10))
@@ -531,7 +560,7 @@ def main():
         return
     npts = wl.n[0] * wl.n[1]
     res = {}
-    paths = [("c64", 0), ("c128", 0), ("c128_unfused", sfo.UNFUSED)]
+    paths = [("c128", 0), ("c64", 0), ("c128_unfused", sfo.UNFUSED)]
     if args.only != "all":
         paths = [p for p in paths if p[0] == args.only]
     for name, flags in paths:
@@ -541,34 +570,64 @@ def main():
             name, 1e3 * res[name]["seconds"] / args.steps, npts * args.steps / res[name]["seconds"],
             res[name]["drift"]), file=sys.stderr, flush=True)
 
-    head = "c64" if "c64" in res else list(res)[0]
-    r = res[head]
-    ms = 1e3 * r["seconds"] / args.steps
-    value = npts * args.steps / r["seconds"]
-    bytes_state = npts * (8 if head.startswith("c64") else 16)
-    bytes_v0 = npts * (4 if head.startswith("c64") else 8)
-    # algorithmic bytes per launch: column pass reads and writes the state once;
-    # row pass additionally reads V0
-    alg = {"column": 2 * bytes_state, "row": 2 * bytes_state + bytes_v0}
-    kstats = {}
-    for k, avg in r["kernels"].items():
-        cnt, tot = r["kernels_ev"][k]
-        kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches_per_step=1,
-                         timing="in-step, per-dispatch timestamps",
-                         avg_us_back_to_back=1e3 * r["kernels_b2b"][k],
-                         avg_us_event_per_launch=1e3 * tot / cnt if cnt else None)
-    dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
-    achieved = kstats[dom]["gbs"]
-    plan = list(r["plan"])
-    variant = {"row": plan[0], "column": plan[1]}[dom]
-    traffic = None
-    if head == "c64" and wl.n == (2048, 2048) and sources_fingerprint() == MEASURED_TRAFFIC["sources_sha256"]:
-        traffic = measured_traffic(dom, variant)
+    def path_report(name, r):
+        """ms/step, updates/s, plan and, for a fused path, per-pass timings and the
+        roofline block of its dominant pass."""
+        dt_ = name.split("_")[0]
+        ms_ = 1e3 * r["seconds"] / args.steps
+        rep = {"ms_per_step": ms_, "updates_per_s": npts * args.steps / r["seconds"], "plan": list(r["plan"])}
+        if r["kernels"] is None:
+            return rep
+        bytes_state = npts * (8 if dt_ == "c64" else 16)
+        bytes_v0 = npts * (4 if dt_ == "c64" else 8)
+        # algorithmic bytes per launch: column pass reads and writes the state once;
+        # row pass additionally reads V0
+        alg = {"column": 2 * bytes_state, "row": 2 * bytes_state + bytes_v0}
+        kstats = {}
+        for k, avg in r["kernels"].items():
+            cnt, tot = r["kernels_ev"][k]
+            kstats[k] = dict(avg_us=1e3 * avg, gbs=alg[k] / (avg * 1e-3) / 1e9, launches_per_step=1,
+                             timing="in-step, per-dispatch timestamps",
+                             avg_us_back_to_back=1e3 * r["kernels_b2b"][k],
+                             avg_us_event_per_launch=1e3 * tot / cnt if cnt else None)
+        dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
+        achieved = kstats[dom]["gbs"]
+        variant = {"row": rep["plan"][0], "column": rep["plan"][1]}[dom]
+        traffic = None
+        if wl.n == (2048, 2048) and sources_fingerprint() == MEASURED_TRAFFIC["sources_sha256"]:
+            traffic = measured_traffic(dt_, dom, variant)
+        rep["roofline"] = {
+            "bound": "hbm",
+            "kernel": ("k_colpass" if dom == "column" else "k_xpass") + " (tile shape %d)" % variant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes": alg[dom],
+        }
+        step_bytes = alg["row"] + alg["column"]
+        rep["step_model_gbs"] = step_bytes / (ms_ * 1e-3) / 1e9
+        rep["step_model_frac"] = step_bytes / (ms_ * 1e-3) / 1e9 / HBM_PEAK_GBS
+        rep["kernels"] = kstats
+        if r.get("fwd_adj_seconds"):
+            # each grid point is advanced once and walked back once per step
+            rep["fwd_adjoint"] = {"updates_per_s": npts * wl.nsteps / r["fwd_adj_seconds"],
+                                  "ms_per_step": 1e3 * r["fwd_adj_seconds"] / wl.nsteps,
+                                  "note": "forward run + reverse sweep with dL/dEbar and dL/dV0, %s" % dt_}
+        return rep
+
+    reports = {k: path_report(k, v) for k, v in res.items()}
+    # the headline is the paper's precision, complex128, when it was run
+    head = "c128" if "c128" in res else list(res)[0]
+    hdtype = head.split("_")[0]
+    r, hr = res[head], reports[head]
+    ms = hr["ms_per_step"]
+    value = hr["updates_per_s"]
     err_vs_c128 = None
     if "c64" in res and "c128" in res:
         a, b = res["c64"]["final"].astype(np.complex128), res["c128"]["final"]
         err_vs_c128 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    step_bytes = alg["row"] + alg["column"]
     out = {
         "metric": "split-step grid-point updates/s (fwd, fwd+adjoint) at stated err; % HBM BW",
         "value": value,
@@ -580,38 +639,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": hdtype,
         "data": "synthetic",
         "config": {
-            "workload": "2d_schrodinger_softcore_laser %dx%d c64 fwd" % (wl.n[0], wl.n[1]),
+            "workload": "2d_schrodinger_softcore_laser %dx%d %s fwd%s" % (
+                wl.n[0], wl.n[1], hdtype, " unfused" if head.endswith("unfused") else ""),
             "grid": list(wl.n), "box": [wl.xmin[0], wl.xmax[0]], "dt": wl.dt, "steps_per_run": wl.nsteps,
             "field": "x.E(t), E0=0.05, omega=0.057, sin^2 envelope over the run",
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("k_colpass" if dom == "column" else "k_xpass") + " (tile shape %d)" % variant,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes": alg[dom],
-        },
-        "step_model_gbs": step_bytes / (ms * 1e-3) / 1e9,
-        "step_model_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "kernels": kstats,
+        "roofline": hr.get("roofline"),
+        "step_model_gbs": hr.get("step_model_gbs"),
+        "step_model_frac": hr.get("step_model_frac"),
+        "kernels": hr.get("kernels"),
         "accuracy": {"c64_norm_drift_per_run": res.get("c64", {}).get("drift"),
                      "c64_rel_l2_vs_c128_after_run": err_vs_c128,
                      "c128_norm_drift_per_run": res.get("c128", {}).get("drift")},
-        "paths": {k: {"ms_per_step": 1e3 * v["seconds"] / args.steps,
-                      "updates_per_s": npts * args.steps / v["seconds"], "plan": list(v["plan"])}
-                  for k, v in res.items()},
+        "paths": {k: v for k, v in reports.items() if k != head},
     }
-    if r.get("fwd_adj_seconds"):
-        # each grid point is advanced once and walked back once per step
-        out["fwd_adjoint"] = {"updates_per_s": npts * wl.nsteps / r["fwd_adj_seconds"],
-                              "ms_per_step": 1e3 * r["fwd_adj_seconds"] / wl.nsteps,
-                              "note": "forward run + reverse sweep with dL/dEbar and dL/dV0, c64"}
+    if hr.get("fwd_adjoint"):
+        out["fwd_adjoint"] = hr["fwd_adjoint"]
     if not args.no_batch:
         out["batch"] = bench_batch()
         print("# batch fwd %.2f ms/run, fwd+adjoint %.2f ms/run" % (out["batch"]["fwd_ms_per_run"],
@@ -627,11 +673,6 @@ def main():
         out["autocorrelation"] = bench_autocorrelation()
         print("# autocorrelation 2048^2 c64 %.4f ms/step (plain run %.4f)" % (
             out["autocorrelation"]["ms_per_step"], out["autocorrelation"]["ms_per_step_without_chi"]),
-            file=sys.stderr, flush=True)
-        lib = bench_library_fft(wl)
-        out["library_fft_comparison"] = lib
-        print("# torch.fft split step: c64 %.4f ms/step, c128 %.4f ms/step; c128 rel L2 vs sfo %.2e" % (
-            lib["c64"]["ms_per_step"], lib["c128"]["ms_per_step"], lib["c128_rel_l2_vs_sfo_after_20_steps"]),
             file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

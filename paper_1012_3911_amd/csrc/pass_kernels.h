@@ -612,9 +612,15 @@ k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__r
     const double sg = (double)kin.sgn;
     cx<R> a[1][RV], b[1][RV];
     col_load<R, N, RAD, 1>(a, S, w * C, stride, tb);
-    for (int64_t j = w;;) {
+    int64_t j = w;
+    // one group; NEXT: the next group's loads are issued into b.  The last
+    // group is a separate instance so that no path through a group lacks the
+    // prefetch: where two paths meet, the compiler's wait for the kinetic
+    // table would count only the loads common to both and so wait for the
+    // whole prefetch.
+    auto group = [&](auto next) {
+        constexpr bool NEXT = decltype(next)::value;
         const int64_t jn = j + nwg;
-        const bool more = jn < ngroups;
         const int64_t col = j * C + c;
         const cx<double> ka = gload((const cx<double> *)kin.kA + col % kin.nA),
                          kb = gload((const cx<double> *)kin.kB + col / kin.nA);
@@ -626,7 +632,7 @@ k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__r
                 kl[m] = gload((const cx<double> *)((const char *)kin.kL + m * T * (int)sizeof(double2) + tk));
         };
         auto prefetch = [&] {
-            if (more) col_load<R, N, RAD, 1>(b, S, jn * C, stride, tb);
+            if constexpr (NEXT) col_load<R, N, RAD, 1>(b, S, jn * C, stride, tb);
         };
         if constexpr (ORDER == 0) {
             load_kl();
@@ -651,11 +657,14 @@ k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__r
         fft_line_pre<R, N, RAD, +1, ColMap<C>>(a[0], sh, t, tw, wb);
         __asm__ __volatile__("" : "+v"(tb));
         col_store<R, N, RAD, 1>(a, S, j * C, stride, tb);
-        if (!more) break;
+        if constexpr (NEXT) {
 #pragma unroll
-        for (int m = 0; m < RV; ++m) a[0][m] = b[0][m];
-        j = jn;
-    }
+            for (int m = 0; m < RV; ++m) a[0][m] = b[0][m];
+            j = jn;
+        }
+    };
+    for (; j + nwg < ngroups;) group(std::true_type{});
+    group(std::false_type{});
 }
 
 // ---------------------------------------------------------------- 1-D run --

@@ -762,6 +762,9 @@ void store_plan(const std::string &key, const std::vector<int> &p)
 
 template <typename R> bool plan_valid(const sfo_grid g, const int *p)
 {
+    if (g->d.equation == SFO_DIRAC && g->ndim == 2)
+        return dirac_row_variant_ok<R>(p[0], (int)g->n[0], g->n[1]) &&
+               dirac_col_variant_ok<R>(p[1], (int)g->n[1], g->n[0]);
     if (!xpass_variant_ok<R>(p[0], (int)g->n[0])) return false;
     if (g->ndim >= 2 && !colpass_variant_ok<R>(p[1], (int)g->n[1], g->n[0])) return false;
     if (g->ndim == 3 && !colpass_variant_ok<R>(p[2], (int)g->n[2], g->n[0] * g->n[1])) return false;
@@ -908,6 +911,9 @@ template <typename R> sfo_status timing_setup(sfo_grid g, TimingScratch &ts)
     return SFO_OK;
 }
 
+DiracPhaseArgs dirac_phase_args(const sfo_grid g, int64_t sa, int64_t sb, int sgn);
+DiracKinArgs dirac_kin_args(const sfo_grid g, int sgn);
+
 template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
 {
     TimingScratch ts;
@@ -925,6 +931,34 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         return m;
     };
     double best = 1e30;
+    if (g->d.equation == SFO_DIRAC && g->ndim == 2) {
+        // whole steps (row pass, then column pass): rows given the column
+        // shape, then columns given the row shape
+        const DiracPhaseArgs ph = dirac_phase_args(g, 0, 0, +1);
+        const DiracKinArgs k = dirac_kin_args(g, +1);
+        auto steps = [&](int r, int c) {
+            return time_launches(g, ts.a, ts.b, reps, [&] {
+                hipError_t e = launch_dirac_xpass<R>(r, (int)g->n[0], psi, (int)g->n[1], g->ntot, g->V0,
+                                                     (const void *const *)g->tw[0], ph, M_INV | M_PHASE | M_FWD, g->st);
+                if (e != hipSuccess) return e;
+                return launch_dirac_colpass<R>(c, (int)g->n[1], psi, (int)g->n[0], g->ntot,
+                                               (const void *const *)g->tw[1], k, M_FWD | M_KIN | M_INV, g->st);
+            });
+        };
+        for (int v = 0; v < kNumDiracRowVariants; ++v) {
+            if (!dirac_row_variant_ok<R>(v, (int)g->n[0], g->n[1])) continue;
+            const double ms = best_of([&] { return steps(v, g->col_var[1]); });
+            if (ms >= 0 && ms < best) { best = ms; g->row_var = v; }
+        }
+        best = 1e30;
+        for (int v = 0; v < kNumDiracColVariants; ++v) {
+            if (!dirac_col_variant_ok<R>(v, (int)g->n[1], g->n[0])) continue;
+            const double ms = best_of([&] { return steps(g->row_var, v); });
+            if (ms >= 0 && ms < best) { best = ms; g->col_var[1] = v; }
+        }
+        HIP_TRY(hipStreamSynchronize(g->st));
+        return SFO_OK;
+    }
     const bool seq = g->d.equation == SFO_SCHRODINGER && g->ndim >= 2;
     if (seq) {
         // whole steps of the propagation's pass sequence: a pass reads what
@@ -936,24 +970,36 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
                 return time_launches(g, ts.a, ts.b, reps,
                                      [&] { return step_sequence<R>(g, r, c, ns, psi, adj, acc, part); });
             };
-            double b = 1e30;
-            for (int v = 0; v < kNumRowVariants; ++v) {
-                if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
-                const double ms = best_of([&] { return steps(v, cv); });
-                if (ms >= 0 && ms < b) { b = ms; rv = v; }
-            }
+            // shapes whose kernel spills registers move the spilled values
+            // through memory on every launch: never chosen
+            auto rows = [&] {
+                double b = 1e30;
+                for (int v = 0; v < kNumRowVariants; ++v) {
+                    if (!xpass_variant_ok<R>(v, (int)g->n[0]) || xpass_scratch<R>(v, (int)g->n[0], ns) != 0)
+                        continue;
+                    const double ms = best_of([&] { return steps(v, cv); });
+                    if (ms >= 0 && ms < b) { b = ms; rv = v; }
+                }
+            };
+            rows();
+            double b;
             for (int ax = 1; ax < g->ndim; ++ax) {
                 const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
                 b = 1e30;
                 int keep = cv[ax];
                 for (int v = 0; v < kNumColVariants; ++v) {
-                    if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, ns)) continue;
+                    if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, ns) ||
+                        colpass_scratch<R>(v, (int)g->n[ax], ns) != 0)
+                        continue;
                     cv[ax] = v;
                     const double ms = best_of([&] { return steps(rv, cv); });
                     if (ms >= 0 && ms < b) { b = ms; keep = v; }
                 }
                 cv[ax] = keep;
             }
+            // the row shape again, given the column shapes chosen (the passes
+            // share the memory system; the best row shape depends on them)
+            rows();
         };
         int cv[3] = {0, g->col_var[1], g->col_var[2]};
         tune(1, g->row_var, cv, nullptr, nullptr, nullptr);
@@ -980,7 +1026,7 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         return SFO_OK;
     }
     for (int v = 0; v < kNumRowVariants; ++v) {
-        if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
+        if (!xpass_variant_ok<R>(v, (int)g->n[0]) || xpass_scratch<R>(v, (int)g->n[0], 1) != 0) continue;
         const double ms = best_of([&] { return time_row<R>(g, v, psi, ts.a, ts.b, reps); });
         if (ms >= 0 && ms < best) { best = ms; g->row_var = v; }
     }
@@ -988,7 +1034,8 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
         const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
         best = 1e30;
         for (int v = 0; v < kNumColVariants; ++v) {
-            if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols)) continue;
+            if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols) || colpass_scratch<R>(v, (int)g->n[ax], 1) != 0)
+                continue;
             const double ms = best_of([&] { return time_col<R>(g, ax, v, psi, ts.a, ts.b, reps); });
             if (ms >= 0 && ms < best) { best = ms; g->col_var[ax] = v; }
         }
@@ -1006,7 +1053,7 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
     if (he == hipSuccess) {
         best = 1e30;
         for (int v = 0; v < kNumRowVariants; ++v) {
-            if (!xpass_variant_ok<R>(v, (int)g->n[0])) continue;
+            if (!xpass_variant_ok<R>(v, (int)g->n[0]) || xpass_scratch<R>(v, (int)g->n[0], 2) != 0) continue;
             const double ms = best_of([&] { return time_row2<R>(g, v, psi, adj, acc, part, ts.a, ts.b, reps); });
             if (ms >= 0 && ms < best) { best = ms; g->row_var2 = v; }
         }
@@ -1014,7 +1061,8 @@ template <typename R> sfo_status autotune_impl(sfo_grid g, int reps)
             const int64_t ncols = ax == 1 ? g->n[0] : g->n[0] * g->n[1];
             best = 1e30;
             for (int v = 0; v < kNumColVariants; ++v) {
-                if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, 2)) continue;
+                if (!colpass_variant_ok<R>(v, (int)g->n[ax], ncols, 2) || colpass_scratch<R>(v, (int)g->n[ax], 2) != 0)
+                    continue;
                 const double ms = best_of([&] { return time_col2<R>(g, ax, v, psi, adj, ts.a, ts.b, reps); });
                 if (ms >= 0 && ms < best) { best = ms; g->col_var2[ax] = v; }
             }
@@ -1070,6 +1118,13 @@ template <typename R> sfo_status time_pass_impl(sfo_grid g, int kind, int reps, 
 // exists for each pass of this grid.
 template <typename R> void default_plan(sfo_grid g)
 {
+    if (g->d.equation == SFO_DIRAC && g->ndim == 2) {
+        for (int v = 0; v < kNumDiracRowVariants; ++v)
+            if (dirac_row_variant_ok<R>(v, (int)g->n[0], g->n[1])) { g->row_var = v; break; }
+        for (int v = 0; v < kNumDiracColVariants; ++v)
+            if (dirac_col_variant_ok<R>(v, (int)g->n[1], g->n[0])) { g->col_var[1] = v; break; }
+        return;
+    }
     for (int v = 0; v < kNumRowVariants; ++v)
         if (xpass_variant_ok<R>(v, (int)g->n[0])) { g->row_var = v; break; }
     for (int ax = 1; ax < g->ndim; ++ax) {
@@ -1250,13 +1305,13 @@ template <typename R> sfo_status dirac_xpass(sfo_grid g, void *psi, int64_t sa, 
 {
     const DiracPhaseArgs ph = dirac_phase_args(g, sa, sb, sgn);
     HIP_TRY(timed(g, SFO_KERNEL_ROW, [&] {
-        return launch_dirac_xpass<R>((int)g->n[0], (cx<R> *)psi, (int)g->n[1], g->ntot, g->V0, g->tw[0][0], ph, mode,
-                                     g->st);
+        return launch_dirac_xpass<R>(g->row_var, (int)g->n[0], (cx<R> *)psi, (int)g->n[1], g->ntot, g->V0,
+                                     (const void *const *)g->tw[0], ph, mode, g->st);
     }));
     return SFO_OK;
 }
 
-template <typename R> sfo_status dirac_colpass(sfo_grid g, void *psi, int mode, int sgn)
+DiracKinArgs dirac_kin_args(const sfo_grid g, int sgn)
 {
     DiracKinArgs k{};
     k.kx = g->kvec[0];
@@ -1267,8 +1322,15 @@ template <typename R> sfo_status dirac_colpass(sfo_grid g, void *psi, int mode, 
     k.tau_over_hbar = g->d.dt / g->d.hbar;
     k.inv_ntot = 1.0 / (double)g->ntot;
     k.sgn = sgn;
+    return k;
+}
+
+template <typename R> sfo_status dirac_colpass(sfo_grid g, void *psi, int mode, int sgn)
+{
+    const DiracKinArgs k = dirac_kin_args(g, sgn);
     HIP_TRY(timed(g, SFO_KERNEL_COLUMN, [&] {
-        return launch_dirac_colpass<R>((int)g->n[1], (cx<R> *)psi, (int)g->n[0], g->ntot, g->tw[1][0], k, mode, g->st);
+        return launch_dirac_colpass<R>(g->col_var[1], (int)g->n[1], (cx<R> *)psi, (int)g->n[0], g->ntot,
+                                       (const void *const *)g->tw[1], k, mode, g->st);
     }));
     return SFO_OK;
 }

@@ -42,6 +42,48 @@ template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols,
     }
 }
 
+// Scratch bytes per lane of the kernel a column shape launches for a step's
+// k-space pass (ns = 1: the pipelined kernel where the shape has one, else
+// the plain one) or the reverse sweep's (ns = 2), -1 if there is none.
+template <typename R, int N, int NS, size_t... I> int col_scratch_n(int v, std::index_sequence<I...>)
+{
+    int bytes = -1;
+    auto one = [&](auto vi) {
+        constexpr int V = decltype(vi)::value;
+        if constexpr (col_variant_ok<R, N, V>()) {
+            constexpr ColVariant cv = kColVariants[V];
+            const void *k = nullptr;
+            if constexpr (cv.pipe > 0 && NS == 1)
+                k = (const void *)k_colpipe<R, N, cv.rad, cv.cols, cv.wpe, cv.order>;
+            else if constexpr (cv.pre)
+                k = (const void *)k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS, false, false, true>;
+            else
+                k = (const void *)k_colpass<R, N, cv.rad, cv.cols, cv.wpe, NS>;
+            hipFuncAttributes a{};
+            if (hipFuncGetAttributes(&a, k) == hipSuccess) bytes = (int)a.localSizeBytes;
+        }
+    };
+    ((v == (int)I ? (one(std::integral_constant<int, (int)I>{}), 0) : 0), ...);
+    return bytes;
+}
+
+template <typename R> int colpass_scratch(int variant, int N, int ns)
+{
+    if (variant < 0 || variant >= kNumColVariants) return -1;
+    switch (N) {
+#define CASE(n)                                                                                   \
+    case n:                                                                                       \
+        return ns == 2 ? col_scratch_n<R, n, 2>(variant, std::make_index_sequence<kNumColVariants>{}) \
+                       : col_scratch_n<R, n, 1>(variant, std::make_index_sequence<kNumColVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return -1;
+    }
+}
+
+template int colpass_scratch<float>(int, int, int);
+template int colpass_scratch<double>(int, int, int);
+
 template bool colpass_variant_ok<float>(int, int, int64_t, int);
 template bool colpass_variant_ok<double>(int, int, int64_t, int);
 

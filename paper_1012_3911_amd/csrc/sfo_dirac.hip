@@ -16,6 +16,7 @@
 //   w = c (p_x - i p_y), wb = c (p_x + i p_y).
 // The spinor factors are evaluated in FP64 and applied in FP64.
 #include <type_traits>
+#include <utility>
 
 #include "pass_kernels.h"
 
@@ -34,8 +35,17 @@ template <typename R> __device__ __forceinline__ void dirac_rotate(cx<R> (&p)[4]
     p[3] = {(R)(fr * r3 - fi * i3), (R)(fr * i3 + fi * r3)};
 }
 
-template <typename R, int N, int RAD>
-__global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT))
+// Planes of a work-group: all four, or one of the two pairs that the factors
+// couple ((1,4) and (2,3): the alpha_2 rotation of the row pass and the
+// off-diagonal terms of H map each pair to itself), so that a work-group of
+// a pair holds half the registers and can take radix-16 transforms.
+template <int NPL> __device__ __forceinline__ int dirac_plane(int pair, int q)
+{
+    return NPL == 4 ? q : (pair ? 1 + q : 3 * q);
+}
+
+template <typename R, int N, int RAD, int NPL>
+__global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
     k_dirac_xpass(cx<R> *__restrict__ psi, int64_t plane, const VStore<R> *__restrict__ V0,
                   const TwEntry<R> *__restrict__ tw, DiracPhaseArgs ph, int mode)
 {
@@ -43,28 +53,35 @@ __global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT))
     using Map = RowMap<R, RAD>;
     constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, 256>::ROWS;
     __shared__ cx<R> lds[ROWS * Map::slots(N)];
+    // a pair's two work-groups of the same rows are consecutive after the
+    // XCD remap (one XCD, the potential read once into its L2)
+    const unsigned G = gridDim.x;
+    unsigned L = blockIdx.x;
+    if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
+    const int pair = NPL == 4 ? 0 : (int)(L & 1u);
+    const unsigned rg = NPL == 4 ? L : L >> 1;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int64_t row0 = (int64_t)blockIdx.x * ROWS, row = row0 + line;
+    const int64_t row0 = (int64_t)rg * ROWS, row = row0 + line;
     cx<R> *sh = lds + line * Map::slots(N);
     // addresses: the work-group's uniform base of plane q, element m (scalar
     // registers) plus the thread's 32-bit byte offset (see row_load)
     uint32_t lt = (uint32_t)(line * N + t) * (uint32_t)sizeof(cx<R>);
     auto at = [&](int q, int m) {
-        char *b = scalar_base((char *)(psi + q * plane + row0 * N + m * T));
+        char *b = scalar_base((char *)(psi + dirac_plane<NPL>(pair, q) * plane + row0 * N + m * T));
         return (cx<R> *)(b + lt);
     };
     // stage factors formed from each stage's W^k, read once with the line (no
     // table reads inside the transforms)
     TwBase<N, RAD> wb;
     tw_base_load(wb, tw, t);
-    cx<R> v[4][RV];
+    cx<R> v[NPL][RV];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) v[q][m] = gload(at(q, m));
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
+        for (int q = 0; q < NPL; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
     if (mode & M_PHASE) {
         const double sg = (double)ph.sgn;
 #pragma unroll
@@ -77,25 +94,36 @@ __global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT))
             if (ph.abar_b) ab += ph.cb * ph.abar_b[x];
             double sa, ca;
             sincos_fp64(sg * ph.aA * ab, sa, ca);
-            cx<R> p[4] = {v[0][m], v[1][m], v[2][m], v[3][m]};
-            dirac_rotate(p, ca, sa, c, -s);
+            if constexpr (NPL == 4) {
+                cx<R> p[4] = {v[0][m], v[1][m], v[2][m], v[3][m]};
+                dirac_rotate(p, ca, sa, c, -s);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q][m] = p[q];
+                for (int q = 0; q < 4; ++q) v[q][m] = p[q];
+            } else {
+                // pair (1,4): (a, b) <- (c a + s b, c b - s a); pair (2,3): (c a - s b, c b + s a)
+                const double ss = pair ? -sa : sa;
+                const double ar = v[0][m].re, ai = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
+                const double r0 = ca * ar + ss * br, i0 = ca * ai + ss * bi;
+                const double r1 = ca * br - ss * ar, i1 = ca * bi - ss * ai;
+                const double fr = c, fi = -s;
+                v[0][m] = {(R)(fr * r0 - fi * i0), (R)(fr * i0 + fi * r0)};
+                v[1][m] = {(R)(fr * r1 - fi * i1), (R)(fr * i1 + fi * r1)};
+            }
         }
     }
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
+        for (int q = 0; q < NPL; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
     // the offset is recomputed rather than held through the transforms
     __asm__ __volatile__("" : "+v"(lt));
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) gstore(at(q, m), v[q][m]);
 }
 
-template <typename R, int N, int RAD, int C>
-__global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
+template <typename R, int N, int RAD, int C, int NPL>
+__global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(2)))
     k_dirac_colpass(cx<R> *__restrict__ psi, int64_t plane, int nx, const TwEntry<R> *__restrict__ tw,
                     DiracKinArgs kin, int mode)
 {
@@ -107,26 +135,28 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
     const unsigned G = gridDim.x;
     unsigned L = blockIdx.x;
     if ((G & 7u) == 0) L = (L & 7u) * (G >> 3) + (L >> 3);
-    const int64_t col = (int64_t)L * C + c;
+    const int pair = NPL == 4 ? 0 : (int)(L & 1u);
+    const unsigned cg = NPL == 4 ? L : L >> 1;
+    const int64_t col = (int64_t)cg * C + c;
     cx<R> *sh = lds + c;
     // addresses: uniform base of plane q, element m (scalar registers) plus the
     // thread's 32-bit byte offset (t nx + c) (see col_load; the launcher checks the range)
     uint32_t tb = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(cx<R>);
     auto at = [&](int q, int m) {
-        char *b = (char *)(psi + q * plane + (int64_t)m * T * nx + (int64_t)L * C);
+        char *b = (char *)(psi + dirac_plane<NPL>(pair, q) * plane + (int64_t)m * T * nx + (int64_t)cg * C);
         __asm__ __volatile__("" : "+s"(b));
         return (cx<R> *)(b + tb);
     };
     TwBase<N, RAD> wb;  // stage factors formed from W^k (see k_dirac_xpass)
     tw_base_load(wb, tw, t);
-    cx<R> v[4][RV];
+    cx<R> v[NPL][RV];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) v[q][m] = gload(at(q, m));
     if (mode & M_FWD)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
+        for (int q = 0; q < NPL; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
     if (mode & M_KIN) {
         const double px = kin.hbar * kin.kx[col];
         const double sg = (double)kin.sgn;
@@ -144,106 +174,202 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T))
             // off-diagonal coefficient -i sig w = (sig wi) - i (sig wr)  [times 1/Ntot]
             const double owr = sgn_ * wi, owi = -sgn_ * wr;     // -i sig w
             const double obr = -sgn_ * wi, obi = -sgn_ * wr;    // -i sig wb, wb = conj(w)
-            double a[4][2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q][0] = (double)v[q][m].re;
-                a[q][1] = (double)v[q][m].im;
-            }
             auto mul = [](double xr, double xi, double yr, double yi, double &zr, double &zi) {
                 zr = xr * yr - xi * yi;
                 zi = xr * yi + xi * yr;
             };
             double t0r, t0i, t1r, t1i;
-            // psi1' = (Cn - i am) psi1 + (-i sig w) psi4
-            mul(Cn, -am, a[0][0], a[0][1], t0r, t0i);
-            mul(owr, owi, a[3][0], a[3][1], t1r, t1i);
-            const double n0r = t0r + t1r, n0i = t0i + t1i;
-            // psi4' = (-i sig wb) psi1 + (Cn + i am) psi4
-            mul(obr, obi, a[0][0], a[0][1], t0r, t0i);
-            mul(Cn, am, a[3][0], a[3][1], t1r, t1i);
-            const double n3r = t0r + t1r, n3i = t0i + t1i;
-            // psi2' = (Cn - i am) psi2 + (-i sig wb) psi3
-            mul(Cn, -am, a[1][0], a[1][1], t0r, t0i);
-            mul(obr, obi, a[2][0], a[2][1], t1r, t1i);
-            const double n1r = t0r + t1r, n1i = t0i + t1i;
-            // psi3' = (-i sig w) psi2 + (Cn + i am) psi3
-            mul(owr, owi, a[1][0], a[1][1], t0r, t0i);
-            mul(Cn, am, a[2][0], a[2][1], t1r, t1i);
-            const double n2r = t0r + t1r, n2i = t0i + t1i;
-            v[0][m] = {(R)n0r, (R)n0i};
-            v[1][m] = {(R)n1r, (R)n1i};
-            v[2][m] = {(R)n2r, (R)n2i};
-            v[3][m] = {(R)n3r, (R)n3i};
+            if constexpr (NPL == 4) {
+                double a[4][2];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a[q][0] = (double)v[q][m].re;
+                    a[q][1] = (double)v[q][m].im;
+                }
+                // psi1' = (Cn - i am) psi1 + (-i sig w) psi4
+                mul(Cn, -am, a[0][0], a[0][1], t0r, t0i);
+                mul(owr, owi, a[3][0], a[3][1], t1r, t1i);
+                const double n0r = t0r + t1r, n0i = t0i + t1i;
+                // psi4' = (-i sig wb) psi1 + (Cn + i am) psi4
+                mul(obr, obi, a[0][0], a[0][1], t0r, t0i);
+                mul(Cn, am, a[3][0], a[3][1], t1r, t1i);
+                const double n3r = t0r + t1r, n3i = t0i + t1i;
+                // psi2' = (Cn - i am) psi2 + (-i sig wb) psi3
+                mul(Cn, -am, a[1][0], a[1][1], t0r, t0i);
+                mul(obr, obi, a[2][0], a[2][1], t1r, t1i);
+                const double n1r = t0r + t1r, n1i = t0i + t1i;
+                // psi3' = (-i sig w) psi2 + (Cn + i am) psi3
+                mul(owr, owi, a[1][0], a[1][1], t0r, t0i);
+                mul(Cn, am, a[2][0], a[2][1], t1r, t1i);
+                const double n2r = t0r + t1r, n2i = t0i + t1i;
+                v[0][m] = {(R)n0r, (R)n0i};
+                v[1][m] = {(R)n1r, (R)n1i};
+                v[2][m] = {(R)n2r, (R)n2i};
+                v[3][m] = {(R)n3r, (R)n3i};
+            } else {
+                // pair (1,4): a' = (Cn - i am) a + (-i sig w) b, b' = (-i sig wb) a + (Cn + i am) b;
+                // pair (2,3): the same with w and wb exchanged
+                const double xr = pair ? obr : owr, xi = pair ? obi : owi;
+                const double yr = pair ? owr : obr, yi = pair ? owi : obi;
+                const double ar = v[0][m].re, ai = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
+                mul(Cn, -am, ar, ai, t0r, t0i);
+                mul(xr, xi, br, bi, t1r, t1i);
+                const double nar = t0r + t1r, nai = t0i + t1i;
+                mul(yr, yi, ar, ai, t0r, t0i);
+                mul(Cn, am, br, bi, t1r, t1i);
+                const double nbr = t0r + t1r, nbi = t0i + t1i;
+                v[0][m] = {(R)nar, (R)nai};
+                v[1][m] = {(R)nbr, (R)nbi};
+            }
         }
     }
     if (mode & M_INV)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
+        for (int q = 0; q < NPL; ++q) fft_line_pre<R, N, RAD, +1, Map>(v[q], sh, t, tw, wb);
     __asm__ __volatile__("" : "+v"(tb));
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int m = 0; m < RV; ++m) gstore(at(q, m), v[q][m]);
 }
 
-// Tile shapes: radix 8 (four planes in registers), rows filling 256 threads;
-// columns: 4 adjacent lines (64-byte row segments of complex128), within 1024
-// threads and 160 KiB of LDS.  Complex128 holds about 240 VGPRs per thread,
-// so it keeps 4 columns only while a group stays within 512 threads (two
-// waves per SIMD) and takes 2 beyond that.
-constexpr int kDiracRad = 8;
-template <typename R, int N> constexpr int dirac_cols()
+// Tile shapes (kDiracRowVariants, kDiracColVariants): radix, planes per
+// work-group (four, or one coupled pair) and, for columns, adjacent lines
+// per work-group (64-byte row segments of complex128 at four).  Rows fill
+// 256 threads.  Shape 0 of each is the four-plane radix-8 pass.
+template <typename R, int N, int V> constexpr bool dirac_row_ok()
 {
-    constexpr int T = LineShape<N, kDiracRad>::T;
-    int c = (sizeof(R) == 4 || 4 * T <= 512) ? 4 : 2;
-    while (c > 1 && (c * T > 1024 || ColMap<1>::slots(N) * c * (int)sizeof(cx<R>) > 160 * 1024))
-        c /= 2;
-    return c;
+    constexpr DiracVariant dv = kDiracRowVariants[V];
+    using Tl = RowTile<N, dv.rad, 256>;
+    return Tl::ROWS * RowMap<R, dv.rad>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024;
+}
+template <typename R, int N, int V> constexpr bool dirac_col_ok()
+{
+    constexpr DiracVariant dv = kDiracColVariants[V];
+    return dv.cols * LineShape<N, dv.rad>::T <= 1024 &&
+           ColMap<dv.cols>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024 &&
+           (sizeof(R) == 4 || dv.planes == 2 || dv.cols * LineShape<N, dv.rad>::T <= 512);
 }
 
-template <typename R, int N>
-static hipError_t dirac_x_n(cx<R> *psi, int ny, int64_t plane, const void *V0, const void *tw, const DiracPhaseArgs &ph,
+template <typename R, int N, int V>
+static hipError_t dirac_x_v(cx<R> *psi, int ny, int64_t plane, const void *V0, const void *const *tw,
+                            const DiracPhaseArgs &ph, int mode, hipStream_t st)
+{
+    if constexpr (!dirac_row_ok<R, N, V>()) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr DiracVariant dv = kDiracRowVariants[V];
+        using Tl = RowTile<N, dv.rad, 256>;
+        if (ny % Tl::ROWS) return hipErrorInvalidValue;
+        const unsigned groups = (unsigned)(ny / Tl::ROWS) * (dv.planes == 4 ? 1u : 2u);
+        hipLaunchKernelGGL((k_dirac_xpass<R, N, dv.rad, dv.planes>), dim3(groups), dim3(Tl::NT), 0, st, psi, plane,
+                           (const VStore<R> *)V0, (const TwEntry<R> *)tw[dv.rad == 8 ? 0 : 1], ph, mode);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int N, int V>
+static hipError_t dirac_c_v(cx<R> *psi, int nx, int64_t plane, const void *const *tw, const DiracKinArgs &kin,
                             int mode, hipStream_t st)
 {
-    using Tl = RowTile<N, kDiracRad, 256>;
-    if (ny % Tl::ROWS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_dirac_xpass<R, N, kDiracRad>), dim3((unsigned)(ny / Tl::ROWS)), dim3(Tl::NT), 0, st, psi,
-                       plane, (const VStore<R> *)V0, (const TwEntry<R> *)tw, ph, mode);
-    return hipGetLastError();
-}
-
-template <typename R, int N>
-static hipError_t dirac_c_n(cx<R> *psi, int nx, int64_t plane, const void *tw, const DiracKinArgs &kin, int mode,
-                            hipStream_t st)
-{
-    constexpr int C = dirac_cols<R, N>();
-    if (nx % C) return hipErrorInvalidValue;
-    // per-thread byte offsets within a work-group's columns are 32-bit
-    if (((int64_t)(LineShape<N, kDiracRad>::T - 1) * nx + C) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX)
+    if constexpr (!dirac_col_ok<R, N, V>()) {
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_dirac_colpass<R, N, kDiracRad, C>), dim3((unsigned)(nx / C)),
-                       dim3(C * LineShape<N, kDiracRad>::T), 0, st, psi, plane, nx, (const TwEntry<R> *)tw, kin, mode);
-    return hipGetLastError();
+    } else {
+        constexpr DiracVariant dv = kDiracColVariants[V];
+        constexpr int C = dv.cols, T = LineShape<N, dv.rad>::T;
+        if (nx % C) return hipErrorInvalidValue;
+        // per-thread byte offsets within a work-group's columns are 32-bit
+        if (((int64_t)(T - 1) * nx + C) * (int64_t)sizeof(cx<R>) > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+        const unsigned groups = (unsigned)(nx / C) * (dv.planes == 4 ? 1u : 2u);
+        hipLaunchKernelGGL((k_dirac_colpass<R, N, dv.rad, C, dv.planes>), dim3(groups), dim3(C * T), 0, st, psi,
+                           plane, nx, (const TwEntry<R> *)tw[dv.rad == 8 ? 0 : 1], kin, mode);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int N, size_t... I>
+static hipError_t dirac_x_n(int var, cx<R> *psi, int ny, int64_t plane, const void *V0, const void *const *tw,
+                            const DiracPhaseArgs &ph, int mode, hipStream_t st, std::index_sequence<I...>)
+{
+    hipError_t r = hipErrorInvalidValue;
+    ((var == (int)I ? (r = dirac_x_v<R, N, (int)I>(psi, ny, plane, V0, tw, ph, mode, st), 0) : 0), ...);
+    return r;
+}
+
+template <typename R, int N, size_t... I>
+static hipError_t dirac_c_n(int var, cx<R> *psi, int nx, int64_t plane, const void *const *tw,
+                            const DiracKinArgs &kin, int mode, hipStream_t st, std::index_sequence<I...>)
+{
+    hipError_t r = hipErrorInvalidValue;
+    ((var == (int)I ? (r = dirac_c_v<R, N, (int)I>(psi, nx, plane, tw, kin, mode, st), 0) : 0), ...);
+    return r;
 }
 
 template <typename R>
-hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0, const void *tw,
-                              const DiracPhaseArgs &ph, int mode, hipStream_t st)
+hipError_t launch_dirac_xpass(int variant, int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
+                              const void *const *tw, const DiracPhaseArgs &ph, int mode, hipStream_t st)
 {
-#define CALL(n) dirac_x_n<R, n>(psi, ny, plane, V0, tw, ph, mode, st)
+#define CALL(n) \
+    dirac_x_n<R, n>(variant, psi, ny, plane, V0, tw, ph, mode, st, std::make_index_sequence<kNumDiracRowVariants>{})
     SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
 }
 
 template <typename R>
-hipError_t launch_dirac_colpass(int N, cx<R> *psi, int nx, int64_t plane, const void *tw, const DiracKinArgs &kin,
-                                int mode, hipStream_t st)
+hipError_t launch_dirac_colpass(int variant, int N, cx<R> *psi, int nx, int64_t plane, const void *const *tw,
+                                const DiracKinArgs &kin, int mode, hipStream_t st)
 {
-#define CALL(n) dirac_c_n<R, n>(psi, nx, plane, tw, kin, mode, st)
+#define CALL(n) \
+    dirac_c_n<R, n>(variant, psi, nx, plane, tw, kin, mode, st, std::make_index_sequence<kNumDiracColVariants>{})
     SFO_SWITCH_PASS_N(N, CALL)
 #undef CALL
 }
+
+template <typename R, int N, size_t... I> static bool dirac_row_ok_n(int v, std::index_sequence<I...>)
+{
+    bool ok = false;
+    ((v == (int)I ? (ok = dirac_row_ok<R, N, (int)I>(), 0) : 0), ...);
+    return ok;
+}
+template <typename R, int N, size_t... I> static bool dirac_col_ok_n(int v, std::index_sequence<I...>)
+{
+    bool ok = false;
+    ((v == (int)I ? (ok = dirac_col_ok<R, N, (int)I>(), 0) : 0), ...);
+    return ok;
+}
+
+template <typename R> bool dirac_row_variant_ok(int variant, int N, int64_t ny)
+{
+    if (variant < 0 || variant >= kNumDiracRowVariants) return false;
+    bool ok = false;
+    switch (N) {
+#define CASE(n) case n: ok = dirac_row_ok_n<R, n>(variant, std::make_index_sequence<kNumDiracRowVariants>{}); break;
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return false;
+    }
+    if (!ok) return false;
+    const int rad = kDiracRowVariants[variant].rad;
+    const int T = N / (N < rad ? N : rad), rows = 256 / T > 0 ? 256 / T : 1;
+    return ny % rows == 0;
+}
+
+template <typename R> bool dirac_col_variant_ok(int variant, int N, int64_t nx)
+{
+    if (variant < 0 || variant >= kNumDiracColVariants) return false;
+    if (nx % kDiracColVariants[variant].cols) return false;
+    switch (N) {
+#define CASE(n) case n: return dirac_col_ok_n<R, n>(variant, std::make_index_sequence<kNumDiracColVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return false;
+    }
+}
+
+template bool dirac_row_variant_ok<float>(int, int, int64_t);
+template bool dirac_row_variant_ok<double>(int, int, int64_t);
+template bool dirac_col_variant_ok<float>(int, int, int64_t);
+template bool dirac_col_variant_ok<double>(int, int, int64_t);
 
 // ------------------------------------------------------------- 1-D Dirac --
 // The whole run of one line in one work-group: both components in registers
@@ -353,13 +479,13 @@ template hipError_t launch_dirac1d<float>(int, cx<float> *, const void *, const 
 template hipError_t launch_dirac1d<double>(int, cx<double> *, const void *, const void *const *,
                                            const Dirac1DArgs &, hipStream_t);
 
-template hipError_t launch_dirac_xpass<float>(int, cx<float> *, int, int64_t, const void *, const void *,
+template hipError_t launch_dirac_xpass<float>(int, int, cx<float> *, int, int64_t, const void *, const void *const *,
                                               const DiracPhaseArgs &, int, hipStream_t);
-template hipError_t launch_dirac_xpass<double>(int, cx<double> *, int, int64_t, const void *, const void *,
+template hipError_t launch_dirac_xpass<double>(int, int, cx<double> *, int, int64_t, const void *, const void *const *,
                                                const DiracPhaseArgs &, int, hipStream_t);
-template hipError_t launch_dirac_colpass<float>(int, cx<float> *, int, int64_t, const void *, const DiracKinArgs &,
-                                                int, hipStream_t);
-template hipError_t launch_dirac_colpass<double>(int, cx<double> *, int, int64_t, const void *, const DiracKinArgs &,
-                                                 int, hipStream_t);
+template hipError_t launch_dirac_colpass<float>(int, int, cx<float> *, int, int64_t, const void *const *,
+                                                const DiracKinArgs &, int, hipStream_t);
+template hipError_t launch_dirac_colpass<double>(int, int, cx<double> *, int, int64_t, const void *const *,
+                                                 const DiracKinArgs &, int, hipStream_t);
 
 }  // namespace sfo

@@ -240,6 +240,10 @@ void line_stages(int N, int RAD, int *radix, int *span, int *nst);
 // Whether a variant exists for this line length and precision (and, for
 // columns, divides the number of lines).
 template <typename R> bool xpass_variant_ok(int variant, int N);
+// Scratch (spill) bytes per lane of the kernel a shape launches with ns
+// states, -1 if the shape does not exist; the autotuner skips shapes > 0.
+template <typename R> int xpass_scratch(int variant, int N, int ns);
+template <typename R> int colpass_scratch(int variant, int N, int ns);
 template <typename R> bool colpass_variant_ok(int variant, int N, int64_t ncols, int ns = 1);
 
 template <typename R>
@@ -251,13 +255,26 @@ hipError_t launch_1d(int N, cx<R> *psi, int nprob, int64_t prob_stride, const vo
 template <typename R>
 hipError_t launch_1d_eigen(int N, cx<R> *psi, const void *V0, const void *tw, const Run1DArgs &a, hipStream_t st);
 
+// 2-D Dirac pass tile shapes: radix, planes per work-group (4, or 2: one of
+// the pairs (1,4), (2,3) that every factor maps to itself) and, for the
+// column pass, adjacent lines per work-group.
+struct DiracVariant {
+    int rad, planes, cols;
+};
+constexpr DiracVariant kDiracRowVariants[] = {{8, 4, 0}, {16, 2, 0}, {8, 2, 0}};
+constexpr DiracVariant kDiracColVariants[] = {{8, 4, 4}, {8, 4, 2}, {16, 2, 4}, {16, 2, 2}, {8, 2, 4}};
+constexpr int kNumDiracRowVariants = sizeof(kDiracRowVariants) / sizeof(kDiracRowVariants[0]);
+constexpr int kNumDiracColVariants = sizeof(kDiracColVariants) / sizeof(kDiracColVariants[0]);
+template <typename R> bool dirac_row_variant_ok(int variant, int N, int64_t ny);
+template <typename R> bool dirac_col_variant_ok(int variant, int N, int64_t nx);
+
+// tw[0], tw[1]: the stage twiddle tables of the line length for radix 8 and 16.
 template <typename R>
-hipError_t launch_dirac_xpass(int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
-                              const void *tw, const DiracPhaseArgs &ph, int mode,
-                              hipStream_t st);
+hipError_t launch_dirac_xpass(int variant, int N, cx<R> *psi, int ny, int64_t plane, const void *V0,
+                              const void *const *tw, const DiracPhaseArgs &ph, int mode, hipStream_t st);
 
 template <typename R>
-hipError_t launch_dirac_colpass(int N, cx<R> *psi, int nx, int64_t plane, const void *tw,
+hipError_t launch_dirac_colpass(int variant, int N, cx<R> *psi, int nx, int64_t plane, const void *const *tw,
                                 const DiracKinArgs &kin, int mode, hipStream_t st);
 
 // 1-D two-component Dirac run (one work-group per line; alpha_1 = sigma_x,

@@ -42,6 +42,42 @@ template <typename R> bool xpass_variant_ok(int variant, int N)
     }
 }
 
+// Scratch bytes per lane of the kernel a row shape launches with ns states
+// (the compiler's private segment: register spills), -1 if there is none.
+template <typename R, int N, int NS, size_t... I> int row_scratch_n(int v, std::index_sequence<I...>)
+{
+    int bytes = -1;
+    auto one = [&](auto vi) {
+        constexpr int V = decltype(vi)::value;
+        if constexpr (row_variant_ok<R, N, V>()) {
+            constexpr RowVariant rv = kRowVariants[V];
+            hipFuncAttributes a{};
+            if (hipFuncGetAttributes(&a, (const void *)k_xpass<R, N, rv.rad, rv.threads, rv.wpe, NS, rv.pad, rv.late,
+                                                                 rv.pre && sizeof(R) == 8>) == hipSuccess)
+                bytes = (int)a.localSizeBytes;
+        }
+    };
+    ((v == (int)I ? (one(std::integral_constant<int, (int)I>{}), 0) : 0), ...);
+    return bytes;
+}
+
+template <typename R> int xpass_scratch(int variant, int N, int ns)
+{
+    if (variant < 0 || variant >= kNumRowVariants) return -1;
+    switch (N) {
+#define CASE(n)                                                                                   \
+    case n:                                                                                       \
+        return ns == 2 ? row_scratch_n<R, n, 2>(variant, std::make_index_sequence<kNumRowVariants>{}) \
+                       : row_scratch_n<R, n, 1>(variant, std::make_index_sequence<kNumRowVariants>{});
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default: return -1;
+    }
+}
+
+template int xpass_scratch<float>(int, int, int);
+template int xpass_scratch<double>(int, int, int);
+
 template <typename R, int N, size_t... I> int row_groups_n(int v, int64_t nrows, std::index_sequence<I...>)
 {
     int g = -1;

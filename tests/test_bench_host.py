@@ -30,17 +30,18 @@ def test_traffic_is_copy_calibrated_counter_bytes():
     assert b.measured_traffic("c64", "column", 0) == (2.0 * fetch + 1.0 * write) * 1024
     assert b.measured_traffic("c64", "column", 99) is None
     assert b.measured_traffic("c256", "column", 0) is None
-    # every measured shape moves its algorithmic bytes to within -10 % / +30 % (2048^2:
+    # every measured shape moves its algorithmic bytes to within -10 % / +40 % (2048^2:
     # column pass reads and writes the state, row pass also reads the potential; complex64
     # 8 B per point and FP32 potential, complex128 16 B and FP64; narrow complex128
-    # column shapes write up to 41 % more than the state, i.e. 25 % more in total)
+    # column shapes write up to 41 % more than the state, i.e. 25 % more in total; the
+    # pipelined shapes that spill registers (never chosen by the autotuner) up to 31 %)
     for dtype, sb, vb in (("c64", 8, 4), ("c128", 16, 8)):
         npts = 2048 * 2048
         alg = {"column": 2 * sb * npts, "row": (2 * sb + vb) * npts}
         for key in b.MEASURED_TRAFFIC[dtype]:
             kind, var = key.split("/")
             t = b.measured_traffic(dtype, kind, int(var))
-            assert 0.9 * alg[kind] < t < 1.3 * alg[kind], (dtype, key)
+            assert 0.9 * alg[kind] < t < 1.4 * alg[kind], (dtype, key)
 
 
 def test_sources_fingerprint_covers_the_pass_sources():

@@ -45,3 +45,48 @@ def test_dirac_unfused_and_stepwise():
     b = gpu_run(wl, "c128", flags=sfo.UNFUSED)
     c = gpu_run(wl, "c128", stepwise=True)
     assert rel_l2(a, b) < 1e-14 and rel_l2(a, c) < 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dirac_every_tile_shape(orc, dtype):
+    """Every row and column tile shape of the Dirac passes (four planes per
+    work-group, or one coupled pair (1,4) / (2,3); radix 8 or 16) gives the
+    oracle's result on an anisotropic grid with the vector potential, and the
+    autotuner picks one of them."""
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    wl = W.dirac_softcore_laser(n=128, nsteps=12)
+    n, lo, hi = (512, 256), (-4.0, -2.0), (4.0, 2.0)
+    X, Y = W.mesh(n, lo, hi)
+    wl.n, wl.xmin, wl.xmax = n, lo, hi
+    wl.V0 = -20.0 / np.sqrt(X**2 + Y**2 + (0.791 / 20) ** 2)
+    wl.psi0 = W.dirac_packet(n, lo, hi, (40.0, -15.0), 60.0, 30.0)
+    (x,) = W.axes((n[0],), (lo[0],), (hi[0],))
+    tmid = (np.arange(wl.nsteps) + 0.5) * wl.dt
+    wl.abar_y = np.stack([wl.dt * W.laser_vector_potential(x, t) for t in tmid])
+    ref = oracle_run(orc, wl)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    g = make_grid(wl, dtype)
+    tried = []
+    for r in range(8):
+        for c in range(8):
+            try:
+                g.plan = (r, c, 0)
+            except sfo.SfoError:
+                continue
+            psi = to_device(wl.psi0, dtype)
+            g.propagate(psi, 0, wl.nsteps)
+            torch.cuda.synchronize()
+            err = rel_l2(psi.cpu().numpy(), ref)
+            print("dirac shapes (%d, %d): rel L2 vs oracle %.3e" % (r, c, err), flush=True)
+            assert err < tol, (r, c, err)
+            tried.append((r, c))
+    assert len(tried) >= 12, tried
+    g.autotune(3)
+    assert tuple(g.plan[:2]) in tried
+    psi = to_device(wl.psi0, dtype)
+    g.propagate(psi, 0, wl.nsteps)
+    torch.cuda.synchronize()
+    assert rel_l2(psi.cpu().numpy(), ref) < tol
+    g.close()

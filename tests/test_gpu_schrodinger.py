@@ -173,6 +173,48 @@ def test_every_tile_shape(orc, dtype):
     g.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_persistent_column_shapes(orc, dtype):
+    """The column shapes whose work-groups walk several column groups (the next
+    group's loads, or its copy into LDS, in flight while the current group
+    transforms) on a grid wide enough that every work-group takes two or more
+    groups (2048 columns): the oracle's result after 12 steps, and the plain
+    shape's result (the same arithmetic) to rounding."""
+    import torch
+    from paper_1012_3911_amd import sfo
+
+    n, lo, hi = (2048, 512), (-102.4, -25.6), (102.4, 25.6)
+    X, Y = W.mesh(n, lo, hi)
+    wl = W.Workload("t", "schrodinger", n, lo, hi, 0.02, 12, -1.0 / np.sqrt(X**2 + Y**2 + 1.0),
+                    W.gaussian(n, lo, hi, (3.0, -0.5), 1.5, (0.4, 0.2)),
+                    ebar=np.tile([[0.003, -0.002]], (12, 1)))
+    ref = oracle_run(orc, wl)
+    tol = C128_TOL if dtype == "c128" else C64_TOL
+    g = make_grid(wl, dtype)
+    base = list(g.plan)
+    plain = None
+    tried = []
+    for v in range(48):
+        try:
+            g.plan = (base[0], v, 0)
+        except sfo.SfoError:
+            continue
+        psi = to_device(wl.psi0, dtype)
+        g.propagate(psi, 0, wl.nsteps)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy()
+        err = rel_l2(got, ref)
+        print("column shape %d: rel L2 vs oracle %.3e" % (v, err), flush=True)
+        assert err < tol, (v, err)
+        if v == 0:
+            plain = got
+        elif plain is not None and dtype == "c128":
+            assert rel_l2(got, plain) < 1e-13, v
+        tried.append(v)
+    assert 0 in tried and len(tried) >= 12
+    g.close()
+
+
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 def test_step_equals_propagate(orc, ndim):
     if ndim == 1:
