@@ -74,11 +74,11 @@ MEASURED_TRAFFIC = {
         "row/0": (49594, 65536), "row/1": (49431, 65536), "row/2": (49561, 65536), "row/3": (49621, 65536),
         "row/4": (49607, 65536), "row/5": (49393, 65536), "row/6": (49457, 65536), "row/7": (49393, 65536),
         "row/8": (49383, 65536), "row/9": (49452, 65536), "row/10": (49576, 65536), "row/11": (49434, 65536),
-        "row/12": (49616, 65536), "row/13": (49388, 65536), "row/14": (49330, 65536), "row/15": (49330, 65536),
+        "row/12": (49616, 65536), "row/13": (49388, 65536), "row/14": (49330, 65536), "row/15": (49327, 65536),
         "row/16": (49331, 65536), "row/17": (50068, 72752), "column/1": (33468, 75018), "column/2": (33986, 90799),
         "column/4": (33457, 76838), "column/5": (34174, 91712), "column/7": (33373, 65706),
-        "column/8": (33373, 87253), "column/9": (41697, 86355), "column/10": (33377, 67984),
-        "column/11": (41697, 86355), "column/12": (33377, 67984), "column/13": (40642, 89698),
+        "column/8": (33373, 87253), "column/9": (41697, 86355), "column/10": (33311, 69639),
+        "column/11": (41697, 86355), "column/12": (33311, 69639), "column/13": (40642, 89698),
         "column/14": (33435, 66256), "column/15": (40642, 89698), "column/16": (33435, 66256),
         "column/18": (33187, 65752), "column/19": (33188, 65862), "column/20": (33330, 79812),
         "column/21": (33318, 79655),
