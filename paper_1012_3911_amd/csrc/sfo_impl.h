@@ -170,7 +170,9 @@ constexpr RowVariant kRowVariants[] = {
     {16, 256, 1, true, true},  {8, 256, 1, false, true},
     // complex128 with the stage factors formed from W^k (for complex64 these equal shapes 0, 11, 12 and 13)
     {16, 256, 1, true, false, true}, {16, 128, 4, true, true, true}, {16, 256, 1, true, true, true},
-    {8, 256, 1, false, true, true}};
+    {8, 256, 1, false, true, true},
+    // radix 16 through the XOR-swizzled LDS map (an address per element; other bank pattern)
+    {16, 128, 4, false, true, true}, {16, 256, 1, false, true, true}};
 constexpr ColVariant kColVariants[] = {
     {16, 8, 1}, {16, 4, 1}, {16, 2, 1}, {16, 16, 1}, {16, 4, 2}, {16, 2, 4}, {8, 8, 1}, {8, 4, 1}, {8, 2, 4},
     // pipelined k-space pass: 2, 4 or 8 column groups per work-group, prefetch at the group start (order 0)
