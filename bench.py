@@ -54,35 +54,35 @@ TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h"]
 TRAFFIC_TABLE = ("sfo_impl.h", b"struct RowVariant {", b"constexpr int kNumColVariants")
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "18483f749abca3a86d29d1eb76708b07aed69294e6d645a65328e3e79cece38b",
+    "sources_sha256": "0b87eae5a4c0b307fd7839139852cd83e3d0d9fc18ec71f1f697a5788461d4f0",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read; the pipelined
     # column shapes that differ only in groups per work-group share one kernel and one entry;
     # shapes whose kernel spills registers (never tuned in) have none
     "c64": {
         "row/0": (24726, 32768), "row/1": (24726, 32768), "row/2": (24720, 32768), "row/3": (24725, 32768),
-        "row/4": (24724, 32768), "row/5": (24703, 32768), "row/6": (24696, 32768), "row/7": (24700, 32768),
+        "row/4": (24724, 32768), "row/5": (24702, 32768), "row/6": (24696, 32768), "row/7": (24700, 32768),
         "row/8": (24692, 32768), "row/9": (24689, 32768), "row/10": (24721, 32768), "row/11": (24725, 32768),
         "row/12": (24721, 32768), "row/13": (24698, 32768), "row/14": (24726, 32768), "row/15": (24725, 32768),
         "row/16": (24721, 32768), "row/17": (24698, 32768), "row/18": (24738, 32768), "row/19": (24738, 32768),
-        "column/0": (16662, 32806), "column/1": (16658, 32778), "column/2": (16660, 33239),
-        "column/4": (16658, 32774), "column/5": (16660, 33220), "column/7": (16767, 32840),
-        "column/8": (16637, 36402), "column/9": (16812, 32771), "column/10": (16820, 32768),
-        "column/11": (16812, 32771), "column/12": (16820, 32768), "column/13": (16848, 32768),
-        "column/14": (16854, 32768), "column/15": (16848, 32768), "column/16": (16854, 32768),
-        "column/17": (16661, 33199), "column/18": (16657, 33030), "column/19": (16650, 33042),
-        "column/20": (16659, 33715), "column/21": (16651, 33810),
+        "column/0": (16658, 32811), "column/1": (16658, 32776), "column/2": (16658, 33254),
+        "column/4": (16658, 32776), "column/5": (16660, 33203), "column/7": (16769, 32792),
+        "column/8": (16627, 34003), "column/9": (16809, 32768), "column/10": (16818, 32768),
+        "column/11": (16809, 32768), "column/12": (16818, 32768), "column/13": (16841, 32768),
+        "column/14": (16856, 32768), "column/15": (16841, 32768), "column/16": (16856, 32768),
+        "column/17": (16662, 33343), "column/18": (16654, 33000), "column/19": (16657, 33031),
+        "column/20": (16655, 33444), "column/21": (16659, 33568), "column/22": (16866, 32770),
     },
     "c128": {
-        "row/0": (49635, 65536), "row/1": (49429, 65536), "row/2": (49556, 65536), "row/3": (49634, 65536),
-        "row/4": (49642, 65536), "row/5": (49391, 65536), "row/6": (49460, 65536), "row/7": (49393, 65536),
-        "row/8": (49384, 65536), "row/9": (49461, 65536), "row/10": (49600, 65536), "row/11": (49434, 65536),
-        "row/12": (49582, 65536), "row/13": (49390, 65536), "row/14": (49330, 65536), "row/15": (49320, 65536),
-        "row/16": (49332, 65536), "row/18": (49331, 65536), "row/19": (49343, 65536), "column/1": (33455, 77192),
-        "column/2": (34073, 91464), "column/4": (33465, 76924), "column/5": (34130, 92365),
-        "column/7": (33373, 65650), "column/8": (33385, 88678), "column/10": (33314, 68888),
-        "column/12": (33314, 68888), "column/14": (33433, 66021), "column/16": (33433, 66021),
-        "column/18": (33185, 65762), "column/19": (33187, 65728), "column/20": (35236, 83651),
-        "column/21": (33368, 81086),
+        "row/0": (49611, 65536), "row/1": (49429, 65536), "row/2": (49556, 65536), "row/3": (49620, 65536),
+        "row/4": (49633, 65536), "row/5": (49391, 65536), "row/6": (49460, 65536), "row/7": (49393, 65536),
+        "row/8": (49384, 65536), "row/9": (49470, 65536), "row/10": (49616, 65536), "row/11": (49435, 65536),
+        "row/12": (49618, 65536), "row/13": (49390, 65536), "row/14": (49331, 65536), "row/15": (49321, 65536),
+        "row/16": (49332, 65536), "row/18": (49332, 65536), "row/19": (49342, 65536), "column/1": (33465, 76733),
+        "column/2": (34034, 91397), "column/4": (33459, 77377), "column/5": (33894, 90334),
+        "column/7": (33373, 65732), "column/8": (33384, 87955), "column/10": (33365, 67914),
+        "column/12": (33365, 67914), "column/14": (33436, 65791), "column/16": (33436, 65791),
+        "column/18": (33187, 65737), "column/19": (33187, 66158), "column/20": (33305, 78777),
+        "column/21": (35648, 82372), "column/22": (33285, 68215),
     },
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters

@@ -535,26 +535,32 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[NV], cx<R> *sh, int t, cons
 // Full N-point transform of the thread's cyclic values (direction DIR), with
 // the LDS exchanges placed by MAP (RowMap<R, RAD> or ColMap<C>).  PRE: the
 // complex64 stage factors come from wb (see TwBase) instead of the table.
-template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int S, int NV>
+// HOOK: called with std::integral_constant<int, S> after stage S (work of
+// the caller's placed between the stages, e.g. loads issued in parts).
+struct NoStageHook {
+    template <int S> __device__ __forceinline__ void operator()(std::integral_constant<int, S>) const {}
+};
+template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int S, int NV, class HOOK = NoStageHook>
 __device__ __forceinline__ void fft_line_st(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                            const TwBase<N, RAD> &wb, bool act)
+                                            const TwBase<N, RAD> &wb, bool act, const HOOK &hook = HOOK{})
 {
     if constexpr (S < LineShape<N, RAD>::NST) {
         fft_stage<R, N, RAD, DIR, S, MAP, PRE>(v, sh, t, tw, wb, act);
-        fft_line_st<R, N, RAD, DIR, MAP, PRE, S + 1>(v, sh, t, tw, wb, act);
+        hook(std::integral_constant<int, S>{});
+        fft_line_st<R, N, RAD, DIR, MAP, PRE, S + 1>(v, sh, t, tw, wb, act, hook);
     }
 }
 
-template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int NV>
+template <typename R, int N, int RAD, int DIR, class MAP, bool PRE, int NV, class HOOK = NoStageHook>
 __device__ __forceinline__ void fft_line_impl(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                              const TwBase<N, RAD> &wb, bool act)
+                                              const TwBase<N, RAD> &wb, bool act, const HOOK &hook = HOOK{})
 {
     // a fresh copy of the thread index per transform: the exchange
     // addresses of two transforms in a row are then not shared (and kept
     // live) between them
     int tt = t;
     __asm__ __volatile__("" : "+v"(tt));
-    fft_line_st<R, N, RAD, DIR, MAP, PRE, 0>(v, sh, tt, tw, wb, act);
+    fft_line_st<R, N, RAD, DIR, MAP, PRE, 0>(v, sh, tt, tw, wb, act, hook);
 }
 
 template <typename R, int N, int RAD, int DIR, class MAP, int NV>
@@ -567,11 +573,11 @@ __device__ __forceinline__ void fft_line(cx<R> (&v)[NV], cx<R> *sh, int t, const
 
 // Either precision with the stage factors formed from wb (PRE): the
 // transforms read no table.
-template <typename R, int N, int RAD, int DIR, class MAP, int NV>
+template <typename R, int N, int RAD, int DIR, class MAP, int NV, class HOOK = NoStageHook>
 __device__ __forceinline__ void fft_line_pre(cx<R> (&v)[NV], cx<R> *sh, int t, const TwEntry<R> *__restrict__ tw,
-                                             const TwBase<N, RAD> &wb)
+                                             const TwBase<N, RAD> &wb, const HOOK &hook = HOOK{})
 {
-    fft_line_impl<R, N, RAD, DIR, MAP, true>(v, sh, t, tw, wb, true);
+    fft_line_impl<R, N, RAD, DIR, MAP, true>(v, sh, t, tw, wb, true, hook);
 }
 
 // The same with the stage factors of a complex64 line taken from wb.

@@ -393,6 +393,20 @@ __device__ __forceinline__ void col_load(cx<R> (&v)[NS][NV], const StatePtrs<R> 
         }
     }
 }
+// elements m in [M0, M1) of each line only (a load issued in parts)
+template <typename R, int N, int RAD, int M0, int M1, int NV>
+__device__ __forceinline__ void col_load_part(cx<R> (&v)[1][NV], const StatePtrs<R> &S, int64_t ubase,
+                                              int64_t stride, uint32_t tb)
+{
+    constexpr int T = LineShape<N, RAD>::T;
+    const char *b = (const char *)(S.p[0] + ubase);
+#pragma unroll
+    for (int m = M0; m < M1; ++m) {
+        const char *bm = b + (int64_t)m * T * stride * (int64_t)sizeof(cx<R>);
+        __asm__ __volatile__("" : "+s"(bm));
+        v[0][m] = gload((const cx<R> *)(bm + tb));
+    }
+}
 template <typename R, int N, int RAD, int NS, int NV>
 __device__ __forceinline__ void col_store(const cx<R> (&v)[NS][NV], const StatePtrs<R> &S,
                                           int64_t ubase, int64_t stride, uint32_t tb)
@@ -582,7 +596,11 @@ k_colpass(StatePtrs<R> S, int64_t stride, int64_t slab_stride, const TwEntry<R> 
 // factors of the group are requested before the prefetch.
 // ORDER 0: kinetic factors and the prefetch at the start of the group (the
 // prefetch overlaps both transforms); ORDER 1: both after the forward
-// transform (fewer registers held through it).
+// transform (fewer registers held through it); ORDER 2: the kinetic factors
+// issued in parts between the stages of the forward transform and the
+// prefetch in parts between those of the inverse transform (a wave that
+// issues all its loads at once waits for the address unit to take them, and
+// then does no arithmetic).
 template <typename R, int N, int RAD, int C, int WPE, int ORDER>
 __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__restrict__ tw, KinArgs kin,
@@ -625,25 +643,45 @@ k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__r
         const cx<double> ka = gload((const cx<double> *)kin.kA + col % kin.nA),
                          kb = gload((const cx<double> *)kin.kB + col / kin.nA);
         cx<double> kl[RV];
-        auto load_kl = [&] {
+        // kinetic factors of elements [M0, M1) of the thread's line
+        auto load_kl = [&](auto m0, auto m1) {
+            constexpr int M0 = decltype(m0)::value, M1 = decltype(m1)::value;
             __asm__ __volatile__("" : "+v"(tk));
 #pragma unroll
-            for (int m = 0; m < RV; ++m)
+            for (int m = M0; m < M1; ++m)
                 kl[m] = gload((const cx<double> *)((const char *)kin.kL + m * T * (int)sizeof(double2) + tk));
         };
+        using Z = std::integral_constant<int, 0>;
+        using F = std::integral_constant<int, RV>;
         auto prefetch = [&] {
             if constexpr (NEXT) col_load<R, N, RAD, 1>(b, S, jn * C, stride, tb);
         };
         if constexpr (ORDER == 0) {
-            load_kl();
+            load_kl(Z{}, F{});
             __builtin_amdgcn_sched_barrier(0);
             prefetch();
             __builtin_amdgcn_sched_barrier(0);
         }
-        fft_line_pre<R, N, RAD, -1, ColMap<C>>(a[0], sh, t, tw, wb);
+        if constexpr (ORDER == 2) {
+            // part k of NST - 1 parts of the factors after stage k of the forward transform
+            // (none after the last stage: the factors are used right after it)
+            constexpr int NST = LineShape<N, RAD>::NST, NP = NST > 1 ? NST - 1 : 1, P = (RV + NP - 1) / NP;
+            auto part = [&](auto st) {
+                constexpr int K = decltype(st)::value;
+                constexpr int M0 = K * P < RV ? K * P : RV, M1 = (K + 1) * P < RV ? (K + 1) * P : RV;
+                if constexpr (M0 < M1) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_kl(std::integral_constant<int, M0>{}, std::integral_constant<int, M1>{});
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            fft_line_pre<R, N, RAD, -1, ColMap<C>>(a[0], sh, t, tw, wb, part);
+        } else {
+            fft_line_pre<R, N, RAD, -1, ColMap<C>>(a[0], sh, t, tw, wb);
+        }
         if constexpr (ORDER == 1) {
             __builtin_amdgcn_sched_barrier(0);
-            load_kl();
+            load_kl(Z{}, F{});
             __builtin_amdgcn_sched_barrier(0);
             prefetch();
             __builtin_amdgcn_sched_barrier(0);
@@ -654,7 +692,24 @@ k_colpipe(StatePtrs<R> S, int64_t stride, int64_t ngroups, const TwEntry<R> *__r
             const double kr = kcr * kl[m].re - kci * kl[m].im, ki = kcr * kl[m].im + kci * kl[m].re;
             a[0][m] = mul_phase(a[0][m], kr, sg * ki);
         }
-        fft_line_pre<R, N, RAD, +1, ColMap<C>>(a[0], sh, t, tw, wb);
+        if constexpr (ORDER == 2 && NEXT) {
+            // part k of NST parts of the prefetch: before the transform (k = 0) and after each
+            // stage but the last
+            constexpr int NST = LineShape<N, RAD>::NST, P = (RV + NST - 1) / NST;
+            auto part = [&](auto st) {
+                constexpr int K = decltype(st)::value + 1;
+                constexpr int M0 = K * P < RV ? K * P : RV, M1 = (K + 1) * P < RV ? (K + 1) * P : RV;
+                if constexpr (M0 < M1) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    col_load_part<R, N, RAD, M0, M1>(b, S, jn * C, stride, tb);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            part(std::integral_constant<int, -1>{});
+            fft_line_pre<R, N, RAD, +1, ColMap<C>>(a[0], sh, t, tw, wb, part);
+        } else {
+            fft_line_pre<R, N, RAD, +1, ColMap<C>>(a[0], sh, t, tw, wb);
+        }
         __asm__ __volatile__("" : "+v"(tb));
         col_store<R, N, RAD, 1>(a, S, j * C, stride, tb);
         if constexpr (NEXT) {

@@ -160,7 +160,9 @@ struct ColVariant {
     int rad, cols, wpe;
     int pipe = 0;        // > 0: a forward step's k-space pass walks this many column groups per work-group,
                          // the next group's loads in flight while the current one transforms (k_colpipe)
-    int order = 0;       // k_colpipe: where the prefetch is issued (0: group start, 1: after the forward transform)
+    int order = 0;       // k_colpipe: where the kinetic factors and the prefetch are issued (0: both at the group
+                         // start, 1: both after the forward transform, 2: in parts between the stages of the
+                         // forward (factors) and inverse (prefetch) transforms)
     bool pre = false;    // stage factors formed from each stage's W^k, read once per work-group (no table per stage)
 };
 constexpr RowVariant kRowVariants[] = {
@@ -181,7 +183,9 @@ constexpr ColVariant kColVariants[] = {
     {16, 2, 2, 4, 0}, {16, 2, 2, 4, 1}, {16, 2, 2, 8, 0}, {16, 2, 2, 8, 1},
     // plain shapes with the stage factors formed from W^k
     {16, 8, 1, 0, 0, true}, {16, 4, 1, 0, 0, true}, {16, 4, 2, 0, 0, true}, {16, 2, 1, 0, 0, true},
-    {16, 2, 4, 0, 0, true}};
+    {16, 2, 4, 0, 0, true},
+    // pipelined, the kinetic factors and the prefetch issued in parts between the transforms' stages
+    {16, 4, 2, 2, 2}};
 constexpr int kNumRowVariants = sizeof(kRowVariants) / sizeof(kRowVariants[0]);
 constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 
