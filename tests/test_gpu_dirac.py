@@ -21,6 +21,18 @@ def test_dirac_small(orc, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dirac_long_potential_phase(orc, dtype):
+    """A step forty times the workload's: the row pass's potential phase
+    |tau V0 / hbar| reaches 0.2 near the nucleus (5e-3 at the workload's step),
+    against the oracle."""
+    wl = W.dirac_softcore_laser(n=128, nsteps=12, dt=4e-4)
+    assert wl.dt * np.abs(wl.V0).max() > 0.125
+    ref = oracle_run(orc, wl)
+    got = gpu_run(wl, dtype)
+    assert rel_l2(got, ref) < (1e-12 if dtype == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_dirac_anisotropic(orc, dtype):
     """nx != ny and unequal box lengths pin the k_x/k_y and plane indexing."""
     wl = W.dirac_softcore_laser(n=128, nsteps=16)
