@@ -44,14 +44,14 @@ template <int NPL> __device__ __forceinline__ int dirac_plane(int pair, int q)
     return NPL == 4 ? q : (pair ? 1 + q : 3 * q);
 }
 
-template <typename R, int N, int RAD, int NPL>
-__global__ void __launch_bounds__((RowTile<N, RAD, 256>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename R, int N, int RAD, int NPL, int THREADS>
+__global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
     k_dirac_xpass(cx<R> *__restrict__ psi, int64_t plane, const VStore<R> *__restrict__ V0,
                   const TwEntry<R> *__restrict__ tw, DiracPhaseArgs ph, int mode)
 {
     using Sh = LineShape<N, RAD>;
     using Map = RowMap<R, RAD>;
-    constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, 256>::ROWS;
+    constexpr int T = Sh::T, RV = Sh::RV, ROWS = RowTile<N, RAD, THREADS>::ROWS;
     __shared__ cx<R> lds[ROWS * Map::slots(N)];
     // a pair's two work-groups of the same rows are consecutive after the
     // XCD remap (one XCD, the potential read once into its L2)
@@ -235,12 +235,13 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amd
 
 // Tile shapes (kDiracRowVariants, kDiracColVariants): radix, planes per
 // work-group (four, or one coupled pair) and, for columns, adjacent lines
-// per work-group (64-byte row segments of complex128 at four).  Rows fill
-// 256 threads.  Shape 0 of each is the four-plane radix-8 pass.
+// per work-group (64-byte row segments of complex128 at four); rows fill
+// 256, 128 or 64 threads (whole rows; more of the smaller work-groups fit a CU).
+// Shape 0 of each is the four-plane radix-8 pass.
 template <typename R, int N, int V> constexpr bool dirac_row_ok()
 {
     constexpr DiracVariant dv = kDiracRowVariants[V];
-    using Tl = RowTile<N, dv.rad, 256>;
+    using Tl = RowTile<N, dv.rad, dv.threads>;
     return Tl::ROWS * RowMap<R, dv.rad>::slots(N) * (int)sizeof(cx<R>) <= 159 * 1024;
 }
 template <typename R, int N, int V> constexpr bool dirac_col_ok()
@@ -259,11 +260,11 @@ static hipError_t dirac_x_v(cx<R> *psi, int ny, int64_t plane, const void *V0, c
         return hipErrorInvalidValue;
     } else {
         constexpr DiracVariant dv = kDiracRowVariants[V];
-        using Tl = RowTile<N, dv.rad, 256>;
+        using Tl = RowTile<N, dv.rad, dv.threads>;
         if (ny % Tl::ROWS) return hipErrorInvalidValue;
         const unsigned groups = (unsigned)(ny / Tl::ROWS) * (dv.planes == 4 ? 1u : 2u);
-        hipLaunchKernelGGL((k_dirac_xpass<R, N, dv.rad, dv.planes>), dim3(groups), dim3(Tl::NT), 0, st, psi, plane,
-                           (const VStore<R> *)V0, (const TwEntry<R> *)tw[dv.rad == 8 ? 0 : 1], ph, mode);
+        hipLaunchKernelGGL((k_dirac_xpass<R, N, dv.rad, dv.planes, dv.threads>), dim3(groups), dim3(Tl::NT), 0, st, psi,
+                           plane, (const VStore<R> *)V0, (const TwEntry<R> *)tw[dv.rad == 8 ? 0 : 1], ph, mode);
         return hipGetLastError();
     }
 }
@@ -349,8 +350,8 @@ template <typename R> bool dirac_row_variant_ok(int variant, int N, int64_t ny)
     default: return false;
     }
     if (!ok) return false;
-    const int rad = kDiracRowVariants[variant].rad;
-    const int T = N / (N < rad ? N : rad), rows = 256 / T > 0 ? 256 / T : 1;
+    const int rad = kDiracRowVariants[variant].rad, thr = kDiracRowVariants[variant].threads;
+    const int T = N / (N < rad ? N : rad), rows = thr / T > 0 ? thr / T : 1;
     return ny % rows == 0;
 }
 

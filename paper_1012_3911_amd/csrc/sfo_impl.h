@@ -262,12 +262,15 @@ template <typename R>
 hipError_t launch_1d_eigen(int N, cx<R> *psi, const void *V0, const void *tw, const Run1DArgs &a, hipStream_t st);
 
 // 2-D Dirac pass tile shapes: radix, planes per work-group (4, or 2: one of
-// the pairs (1,4), (2,3) that every factor maps to itself) and, for the
-// column pass, adjacent lines per work-group.
+// the pairs (1,4), (2,3) that every factor maps to itself), for the column
+// pass adjacent lines per work-group, for the row pass threads per
+// work-group (whole rows).
 struct DiracVariant {
     int rad, planes, cols;
+    int threads = 256;
 };
-constexpr DiracVariant kDiracRowVariants[] = {{8, 4, 0}, {16, 2, 0}, {8, 2, 0}};
+constexpr DiracVariant kDiracRowVariants[] = {{8, 4, 0},       {16, 2, 0},      {8, 2, 0},
+                                             {16, 2, 0, 128}, {8, 2, 0, 128},  {16, 2, 0, 64}};
 constexpr DiracVariant kDiracColVariants[] = {{8, 4, 4}, {8, 4, 2}, {16, 2, 4}, {16, 2, 2}, {8, 2, 4}};
 constexpr int kNumDiracRowVariants = sizeof(kDiracRowVariants) / sizeof(kDiracRowVariants[0]);
 constexpr int kNumDiracColVariants = sizeof(kDiracColVariants) / sizeof(kDiracColVariants[0]);
