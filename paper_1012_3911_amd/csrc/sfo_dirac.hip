@@ -122,6 +122,74 @@ __global__ void __launch_bounds__((RowTile<N, RAD, THREADS>::NT)) __attribute__(
         for (int m = 0; m < RV; ++m) gstore(at(q, m), v[q][m]);
 }
 
+// Dirac momentum-space factor at element m of the thread's points (k-space
+// values of all four planes, or of one coupled pair), in FP64:
+// (1/Ntot) [cos(E tau/hbar) - i sgn sin(E tau/hbar) H/E] at p = hbar (kx, ky).
+template <typename R, int NPL, int NV>
+__device__ __forceinline__ void dirac_kin_point(cx<R> (&v)[NPL][NV], int m, double px, double py,
+                                                const DiracKinArgs &kin, int pair)
+{
+    const double sg = (double)kin.sgn;
+    const double E = sqrt(kin.mc2 * kin.mc2 + kin.c * kin.c * (px * px + py * py));
+    double sE, cE;
+    sincos_fp64(E * kin.tau_over_hbar, sE, cE);
+    const double sig = sg * sE / E;
+    // U = C - i sig H, scaled by 1/Ntot
+    const double Cn = cE * kin.inv_ntot, sgn_ = sig * kin.inv_ntot;
+    const double am = sgn_ * kin.mc2;              // diag: Cn -+ i am
+    const double wr = kin.c * px, wi = -kin.c * py; // w = c (px - i py)
+    // off-diagonal coefficient -i sig w = (sig wi) - i (sig wr)  [times 1/Ntot]
+    const double owr = sgn_ * wi, owi = -sgn_ * wr;     // -i sig w
+    const double obr = -sgn_ * wi, obi = -sgn_ * wr;    // -i sig wb, wb = conj(w)
+    auto mul = [](double xr, double xi, double yr, double yi, double &zr, double &zi) {
+        zr = xr * yr - xi * yi;
+        zi = xr * yi + xi * yr;
+    };
+    double t0r, t0i, t1r, t1i;
+    if constexpr (NPL == 4) {
+        double a[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q][0] = (double)v[q][m].re;
+            a[q][1] = (double)v[q][m].im;
+        }
+        // psi1' = (Cn - i am) psi1 + (-i sig w) psi4
+        mul(Cn, -am, a[0][0], a[0][1], t0r, t0i);
+        mul(owr, owi, a[3][0], a[3][1], t1r, t1i);
+        const double n0r = t0r + t1r, n0i = t0i + t1i;
+        // psi4' = (-i sig wb) psi1 + (Cn + i am) psi4
+        mul(obr, obi, a[0][0], a[0][1], t0r, t0i);
+        mul(Cn, am, a[3][0], a[3][1], t1r, t1i);
+        const double n3r = t0r + t1r, n3i = t0i + t1i;
+        // psi2' = (Cn - i am) psi2 + (-i sig wb) psi3
+        mul(Cn, -am, a[1][0], a[1][1], t0r, t0i);
+        mul(obr, obi, a[2][0], a[2][1], t1r, t1i);
+        const double n1r = t0r + t1r, n1i = t0i + t1i;
+        // psi3' = (-i sig w) psi2 + (Cn + i am) psi3
+        mul(owr, owi, a[1][0], a[1][1], t0r, t0i);
+        mul(Cn, am, a[2][0], a[2][1], t1r, t1i);
+        const double n2r = t0r + t1r, n2i = t0i + t1i;
+        v[0][m] = {(R)n0r, (R)n0i};
+        v[1][m] = {(R)n1r, (R)n1i};
+        v[2][m] = {(R)n2r, (R)n2i};
+        v[3][m] = {(R)n3r, (R)n3i};
+    } else {
+        // pair (1,4): a' = (Cn - i am) a + (-i sig w) b, b' = (-i sig wb) a + (Cn + i am) b;
+        // pair (2,3): the same with w and wb exchanged
+        const double xr = pair ? obr : owr, xi = pair ? obi : owi;
+        const double yr = pair ? owr : obr, yi = pair ? owi : obi;
+        const double ar = v[0][m].re, ai = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
+        mul(Cn, -am, ar, ai, t0r, t0i);
+        mul(xr, xi, br, bi, t1r, t1i);
+        const double nar = t0r + t1r, nai = t0i + t1i;
+        mul(yr, yi, ar, ai, t0r, t0i);
+        mul(Cn, am, br, bi, t1r, t1i);
+        const double nbr = t0r + t1r, nbi = t0i + t1i;
+        v[0][m] = {(R)nar, (R)nai};
+        v[1][m] = {(R)nbr, (R)nbi};
+    }
+}
+
 template <typename R, int N, int RAD, int C, int NPL>
 __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amdgpu_waves_per_eu(2)))
     k_dirac_colpass(cx<R> *__restrict__ psi, int64_t plane, int nx, const TwEntry<R> *__restrict__ tw,
@@ -159,69 +227,8 @@ __global__ void __launch_bounds__((C * LineShape<N, RAD>::T)) __attribute__((amd
         for (int q = 0; q < NPL; ++q) fft_line_pre<R, N, RAD, -1, Map>(v[q], sh, t, tw, wb);
     if (mode & M_KIN) {
         const double px = kin.hbar * kin.kx[col];
-        const double sg = (double)kin.sgn;
 #pragma unroll
-        for (int m = 0; m < RV; ++m) {
-            const double py = kin.hbar * kin.ky[t + m * T];
-            const double E = sqrt(kin.mc2 * kin.mc2 + kin.c * kin.c * (px * px + py * py));
-            double sE, cE;
-            sincos_fp64(E * kin.tau_over_hbar, sE, cE);
-            const double sig = sg * sE / E;
-            // U = C - i sig H, scaled by 1/Ntot
-            const double Cn = cE * kin.inv_ntot, sgn_ = sig * kin.inv_ntot;
-            const double am = sgn_ * kin.mc2;              // diag: Cn -+ i am
-            const double wr = kin.c * px, wi = -kin.c * py; // w = c (px - i py)
-            // off-diagonal coefficient -i sig w = (sig wi) - i (sig wr)  [times 1/Ntot]
-            const double owr = sgn_ * wi, owi = -sgn_ * wr;     // -i sig w
-            const double obr = -sgn_ * wi, obi = -sgn_ * wr;    // -i sig wb, wb = conj(w)
-            auto mul = [](double xr, double xi, double yr, double yi, double &zr, double &zi) {
-                zr = xr * yr - xi * yi;
-                zi = xr * yi + xi * yr;
-            };
-            double t0r, t0i, t1r, t1i;
-            if constexpr (NPL == 4) {
-                double a[4][2];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a[q][0] = (double)v[q][m].re;
-                    a[q][1] = (double)v[q][m].im;
-                }
-                // psi1' = (Cn - i am) psi1 + (-i sig w) psi4
-                mul(Cn, -am, a[0][0], a[0][1], t0r, t0i);
-                mul(owr, owi, a[3][0], a[3][1], t1r, t1i);
-                const double n0r = t0r + t1r, n0i = t0i + t1i;
-                // psi4' = (-i sig wb) psi1 + (Cn + i am) psi4
-                mul(obr, obi, a[0][0], a[0][1], t0r, t0i);
-                mul(Cn, am, a[3][0], a[3][1], t1r, t1i);
-                const double n3r = t0r + t1r, n3i = t0i + t1i;
-                // psi2' = (Cn - i am) psi2 + (-i sig wb) psi3
-                mul(Cn, -am, a[1][0], a[1][1], t0r, t0i);
-                mul(obr, obi, a[2][0], a[2][1], t1r, t1i);
-                const double n1r = t0r + t1r, n1i = t0i + t1i;
-                // psi3' = (-i sig w) psi2 + (Cn + i am) psi3
-                mul(owr, owi, a[1][0], a[1][1], t0r, t0i);
-                mul(Cn, am, a[2][0], a[2][1], t1r, t1i);
-                const double n2r = t0r + t1r, n2i = t0i + t1i;
-                v[0][m] = {(R)n0r, (R)n0i};
-                v[1][m] = {(R)n1r, (R)n1i};
-                v[2][m] = {(R)n2r, (R)n2i};
-                v[3][m] = {(R)n3r, (R)n3i};
-            } else {
-                // pair (1,4): a' = (Cn - i am) a + (-i sig w) b, b' = (-i sig wb) a + (Cn + i am) b;
-                // pair (2,3): the same with w and wb exchanged
-                const double xr = pair ? obr : owr, xi = pair ? obi : owi;
-                const double yr = pair ? owr : obr, yi = pair ? owi : obi;
-                const double ar = v[0][m].re, ai = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
-                mul(Cn, -am, ar, ai, t0r, t0i);
-                mul(xr, xi, br, bi, t1r, t1i);
-                const double nar = t0r + t1r, nai = t0i + t1i;
-                mul(yr, yi, ar, ai, t0r, t0i);
-                mul(Cn, am, br, bi, t1r, t1i);
-                const double nbr = t0r + t1r, nbi = t0i + t1i;
-                v[0][m] = {(R)nar, (R)nai};
-                v[1][m] = {(R)nbr, (R)nbi};
-            }
-        }
+        for (int m = 0; m < RV; ++m) dirac_kin_point<R, NPL>(v, m, px, kin.hbar * kin.ky[t + m * T], kin, pair);
     }
     if (mode & M_INV)
 #pragma unroll
