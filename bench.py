@@ -126,6 +126,8 @@ def parse():
                    help="only run the other workloads (1-D harmonic, 1-D Dirac, 3-D wells, 2-D Dirac)")
     p.add_argument("--library-fft", action="store_true",
                    help="only time the torch.fft (hipFFT/rocFFT) split step of the workload (a comparison point)")
+    p.add_argument("--batch-only", action="store_true",
+                   help="only run the 64-problem batched control line (forward, forward + reverse sweep)")
     return p.parse_args()
 
 
@@ -554,6 +556,9 @@ def main():
         return
     if args.other_workloads:
         print(json.dumps(bench_configs()))
+        return
+    if args.batch_only:
+        print(json.dumps(bench_batch(reps=1)))
         return
     wl = W.softcore_2d_laser(n=args.n)
     if args.library_fft:

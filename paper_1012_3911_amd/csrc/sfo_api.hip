@@ -1416,6 +1416,10 @@ struct sfo_batch_s {
     hipStream_t cap = nullptr;   // private streams the graphs are captured on
     hipStream_t side = nullptr;  //   (1-D whole runs go on the side branch)
     hipEvent_t fork = nullptr, join = nullptr;
+    // captured graphs: each 2-D group's sequence on a branch of its own (the
+    // groups' problems are independent, so their launches may overlap)
+    std::vector<hipStream_t> br;
+    std::vector<hipEvent_t> br_join;
     struct Group {
         int ndim, nx, ny;
         int off, count;  // ids[off .. off+count)
@@ -1446,6 +1450,10 @@ void free_batch(sfo_batch b)
     for (auto &gr : b->graphs) (void)hipGraphExecDestroy(gr.exec);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
+    for (hipEvent_t e : b->br_join)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t q : b->br)
+        if (q) (void)hipStreamDestroy(q);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->side) (void)hipStreamDestroy(b->side);
     (void)hipFree(b->ids_d);
@@ -1587,43 +1595,57 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
                     : launch_1d_adjoint<R>(G.nx, nullptr, nullptr, nullptr, G.rep->tw[0][1], a, 0.0, nullptr,
                                            nullptr, s1, grp, G.count);
     }
-    // 2-D problems: the fused single-grid sequence, each pass once per group
-    auto xpass = [&](int64_t sa, int64_t sb, int mode, int64_t jmom, double wmul, int init) {
-        for (const auto &G : b->groups) {
-            if (e != hipSuccess || G.ndim != 2) continue;
+    // 2-D problems: the fused single-grid sequence of each group (a launch
+    // covers the group's problems), on the group's own branch when side
+    // branches are given (capture), otherwise one group after the other on s
+    auto group_seq = [&](const sfo_batch_s::Group &G, hipStream_t gs) {
+        auto xpass = [&](int64_t sa, int64_t sb, int mode, int64_t jmom, double wmul, int init) {
+            if (e != hipSuccess) return;
             PhaseArgs ph{};
             ph.sgn = dir;
-            e = launch_xpass<R>(row_shape(G.rep, ns), G.nx, ns, none, G.ny, G.ny, nullptr, (const void *const *)G.rep->tw[0],
-                                ph, GradArgs{}, mode, s, grp_of(G, sa, sb, jmom, wmul, init), G.count);
-        }
-    };
-    auto colpass = [&]() {
-        for (const auto &G : b->groups) {
-            if (e != hipSuccess || G.ndim != 2) continue;
+            e = launch_xpass<R>(row_shape(G.rep, ns), G.nx, ns, none, G.ny, G.ny, nullptr,
+                                (const void *const *)G.rep->tw[0], ph, GradArgs{}, mode, gs,
+                                grp_of(G, sa, sb, jmom, wmul, init), G.count);
+        };
+        auto colpass = [&]() {
+            if (e != hipSuccess) return;
             KinArgs k{nullptr, nullptr, nullptr, 1, dir};
             e = launch_colpass<R>(col_shape(G.rep, 1, ns), G.ny, ns, none, G.nx, G.nx, 1, 0,
-                                  (const void *const *)G.rep->tw[1], k, M_FWD | M_KIN | M_INV, s,
+                                  (const void *const *)G.rep->tw[1], k, M_FWD | M_KIN | M_INV, gs,
                                   grp_of(G, -1, -1, 0, 1.0, 0), G.count);
-        }
-    };
-    if (dir > 0) {
-        if (nsteps > 0) {
-            xpass(-1, step0, M_PHASE | M_FWD, 0, 1.0, 0);
-            for (int64_t j = 0; j < nsteps; ++j) {
+        };
+        if (dir > 0) {
+            if (nsteps > 0) {
+                xpass(-1, step0, M_PHASE | M_FWD, 0, 1.0, 0);
+                for (int64_t j = 0; j < nsteps; ++j) {
+                    colpass();
+                    const bool more = j + 1 < nsteps;
+                    xpass(step0 + j, more ? step0 + j + 1 : -1, M_INV | M_PHASE | (more ? M_FWD : 0), 0, 1.0, 0);
+                }
+            }
+        } else {
+            // reverse sweep (as schro_adjoint): boundary nsteps first, then each step backwards
+            xpass(-1, nsteps > 0 ? step0 + nsteps - 1 : -1, nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD, nsteps,
+                  1.0, 1);
+            for (int64_t j = nsteps - 1; j >= 0; --j) {
                 colpass();
-                const bool more = j + 1 < nsteps;
-                xpass(step0 + j, more ? step0 + j + 1 : -1, M_INV | M_PHASE | (more ? M_FWD : 0), 0, 1.0, 0);
+                xpass(step0 + j, j > 0 ? step0 + j - 1 : -1, M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), j,
+                      j > 0 ? 2.0 : 1.0, 0);
             }
         }
-    } else {
-        // reverse sweep (as schro_adjoint): boundary nsteps first, then each step backwards
-        xpass(-1, nsteps > 0 ? step0 + nsteps - 1 : -1, nsteps > 0 ? (M_PHASE | M_FWD | M_GRAD) : M_GRAD, nsteps, 1.0,
-              1);
-        for (int64_t j = nsteps - 1; j >= 0; --j) {
-            colpass();
-            xpass(step0 + j, j > 0 ? step0 + j - 1 : -1, M_INV | M_PHASE | M_GRAD | (j > 0 ? M_FWD : 0), j,
-                  j > 0 ? 2.0 : 1.0, 0);
+    };
+    size_t k2 = 0;
+    for (const auto &G : b->groups) {
+        if (e != hipSuccess || G.ndim != 2) continue;
+        const bool own = side && k2 < b->br.size();
+        hipStream_t gs = own ? b->br[k2] : s;
+        if (own) e = hipStreamWaitEvent(gs, b->fork, 0);
+        group_seq(G, gs);
+        if (e == hipSuccess && own) {
+            e = hipEventRecord(b->br_join[k2], gs);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->br_join[k2], 0);
         }
+        ++k2;
     }
     if (e == hipSuccess && side) {
         e = hipEventRecord(b->join, side);
@@ -2157,6 +2179,13 @@ sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stre
     if (e == hipSuccess) e = hipStreamCreate(&b->side);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+    for (const auto &G : b->groups) {
+        if (e != hipSuccess || G.ndim != 2) continue;
+        b->br.push_back(nullptr);
+        b->br_join.push_back(nullptr);
+        e = hipStreamCreate(&b->br.back());
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->br_join.back(), hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = dev_malloc(&b->ids_d, sizeof(int) * b->ids.size());
     if (e == hipSuccess) e = hipMemcpy(b->ids_d, b->ids.data(), sizeof(int) * b->ids.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
