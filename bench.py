@@ -216,6 +216,7 @@ def bench_batch(reps=3):
     psis = [torch.from_numpy(wl.psi0).to("cuda").to(torch.complex64).contiguous() for wl in wls]
     gs = [torch.from_numpy(t).to("cuda").to(torch.complex64).contiguous() for t in targets]
     b = sfo.Batch(grids)
+    b.autotune(10)  # shapes of the grouped launches (one launch covers a group's problems)
     b.propagate(psis, 0, S)
     b.adjoint(psis, gs, 0, S)
     b.check()

@@ -772,17 +772,21 @@ template <typename R> bool plan_valid(const sfo_grid g, const int *p)
 }
 
 // Milliseconds of `reps` launches of fn (after two warm-up launches); -1 if a launch fails.
-template <typename F> double time_launches(sfo_grid g, hipEvent_t a, hipEvent_t b, int reps, F &&fn)
+template <typename F> double time_launches_on(hipStream_t st, hipEvent_t a, hipEvent_t b, int reps, F &&fn)
 {
     for (int i = 0; i < 2; ++i)
         if (fn() != hipSuccess) return -1.0;
-    if (hipEventRecord(a, g->st) != hipSuccess) return -1.0;
+    if (hipEventRecord(a, st) != hipSuccess) return -1.0;
     for (int i = 0; i < reps; ++i)
         if (fn() != hipSuccess) return -1.0;
-    if (hipEventRecord(b, g->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1.0;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1.0;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
     return ms;
+}
+template <typename F> double time_launches(sfo_grid g, hipEvent_t a, hipEvent_t b, int reps, F &&fn)
+{
+    return time_launches_on(g->st, a, b, reps, fn);
 }
 
 // Back-to-back launches of one pass shape on a scratch state (row pass:
@@ -1424,6 +1428,9 @@ struct sfo_batch_s {
         int ndim, nx, ny;
         int off, count;  // ids[off .. off+count)
         sfo_grid rep;    // a grid of the group: its tables and tile shapes serve all
+        // the forward passes' shapes chosen for the grouped launches
+        // (sfo_batch_autotune); -1: those of rep
+        int row_f = -1, col_f = -1;
     };
     std::vector<Group> groups;
     std::vector<int> ids;
@@ -1533,14 +1540,18 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
 // The tile shapes of every 2-D group's passes: a captured graph holds launches
 // of these shapes (grid sizes, and in the reverse sweep the partial-slot
 // stride of the row pass), so it is valid only while they are unchanged.
+// Shapes of a 2-D group's grouped launches with ns states.
+int group_row(const sfo_batch_s::Group &G, int ns) { return ns == 1 && G.row_f >= 0 ? G.row_f : row_shape(G.rep, ns); }
+int group_col(const sfo_batch_s::Group &G, int ns) { return ns == 1 && G.col_f >= 0 ? G.col_f : col_shape(G.rep, 1, ns); }
+
 std::vector<int> batch_shapes(const sfo_batch b)
 {
     std::vector<int> v;
     for (const auto &G : b->groups)
         if (G.ndim == 2)
             for (int ns = 1; ns <= 2; ++ns) {
-                v.push_back(row_shape(G.rep, ns));
-                v.push_back(col_shape(G.rep, 1, ns));
+                v.push_back(group_row(G, ns));
+                v.push_back(group_col(G, ns));
             }
     return v;
 }
@@ -1548,7 +1559,8 @@ std::vector<int> batch_shapes(const sfo_batch b)
 // The launches of one batched run on stream s (1-D whole runs on `side`
 // when it is given, joined back before the end).
 template <typename R>
-hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hipStream_t s, hipStream_t side)
+hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hipStream_t s, hipStream_t side,
+                         int only = -1)
 {
     const BatchProb<R> *pd = (const BatchProb<R> *)b->probs_d;
     const int ns = dir < 0 ? 2 : 1;
@@ -1585,7 +1597,7 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
         if (e == hipSuccess) e = hipStreamWaitEvent(side, b->fork, 0);
     }
     for (const auto &G : b->groups) {
-        if (e != hipSuccess || G.ndim != 1) continue;
+        if (e != hipSuccess || G.ndim != 1 || only >= 0) continue;
         Run1DArgs a{};
         a.step0 = step0;
         a.nsteps = nsteps;
@@ -1603,14 +1615,14 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
             if (e != hipSuccess) return;
             PhaseArgs ph{};
             ph.sgn = dir;
-            e = launch_xpass<R>(row_shape(G.rep, ns), G.nx, ns, none, G.ny, G.ny, nullptr,
+            e = launch_xpass<R>(group_row(G, ns), G.nx, ns, none, G.ny, G.ny, nullptr,
                                 (const void *const *)G.rep->tw[0], ph, GradArgs{}, mode, gs,
                                 grp_of(G, sa, sb, jmom, wmul, init), G.count);
         };
         auto colpass = [&]() {
             if (e != hipSuccess) return;
             KinArgs k{nullptr, nullptr, nullptr, 1, dir};
-            e = launch_colpass<R>(col_shape(G.rep, 1, ns), G.ny, ns, none, G.nx, G.nx, 1, 0,
+            e = launch_colpass<R>(group_col(G, ns), G.ny, ns, none, G.nx, G.nx, 1, 0,
                                   (const void *const *)G.rep->tw[1], k, M_FWD | M_KIN | M_INV, gs,
                                   grp_of(G, -1, -1, 0, 1.0, 0), G.count);
         };
@@ -1637,6 +1649,10 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
     size_t k2 = 0;
     for (const auto &G : b->groups) {
         if (e != hipSuccess || G.ndim != 2) continue;
+        if (only >= 0 && &G != &b->groups[(size_t)only]) {
+            ++k2;
+            continue;
+        }
         const bool own = side && k2 < b->br.size();
         hipStream_t gs = own ? b->br[k2] : s;
         if (own) e = hipStreamWaitEvent(gs, b->fork, 0);
@@ -1653,6 +1669,74 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
     }
     if (e == hipSuccess && dir < 0) e = launch_batch_ebar_grad<R>(pd, (int)b->grids.size(), nsteps, s);
     return e;
+}
+
+// Tile shapes of the grouped forward launches (sfo_batch_autotune): each 2-D
+// group's sequence alone, `reps` steps on scratch states, rows given the
+// column shape, then columns given the row shape.
+template <typename R> sfo_status batch_tune(sfo_batch b, int reps)
+{
+    const int n = (int)b->grids.size();
+    size_t total = 0;
+    for (const sfo_grid g : b->grids) total += (size_t)g->ntot;
+    HIP_TRY(hipStreamSynchronize(b->st));
+    TimingScratch ts;
+    HIP_TRY(dev_malloc(&ts.mem, sizeof(cx<R>) * total));
+    HIP_TRY(hipMemsetAsync(ts.mem, 0, sizeof(cx<R>) * total, b->st));
+    HIP_TRY(hipEventCreate(&ts.a));
+    HIP_TRY(hipEventCreate(&ts.b));
+    std::vector<void *> ptr((size_t)n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        ptr[(size_t)i] = (cx<R> *)ts.mem + off;
+        off += (size_t)b->grids[(size_t)i]->ntot;
+    }
+    int64_t need = 0;
+    const std::vector<BatchProb<R>> P = batch_probs<R>(b, ptr.data(), nullptr, nullptr, nullptr, 0, &need);
+    const size_t bytes = sizeof(BatchProb<R>) * P.size();
+    HIP_TRY(hipMemcpy(b->probs_d, P.data(), bytes, hipMemcpyHostToDevice));
+    b->probs_h.assign((const char *)P.data(), (const char *)P.data() + bytes);
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        sfo_batch_s::Group &G = b->groups[gi];
+        if (G.ndim != 2) continue;
+        // steps within every member's field table
+        int64_t steps = reps;
+        for (int k = 0; k < G.count; ++k) {
+            const sfo_grid g = b->grids[(size_t)b->ids[(size_t)(G.off + k)]];
+            if (g->ebar_steps > 0) steps = std::min<int64_t>(steps, g->ebar_steps);
+        }
+        auto time_seq = [&]() {
+            double best = -1.0;
+            for (int trial = 0; trial < 3; ++trial) {
+                const double ms = time_launches_on(b->st, ts.a, ts.b, 1, [&] {
+                    return batch_enqueue<R>(b, +1, 0, steps, b->st, nullptr, (int)gi);
+                });
+                if (ms >= 0 && (best < 0 || ms < best)) best = ms;
+            }
+            return best;
+        };
+        G.row_f = row_shape(G.rep, 1);
+        G.col_f = col_shape(G.rep, 1, 1);
+        double best = time_seq();
+        int keep = G.row_f;
+        for (int v = 0; v < kNumRowVariants; ++v) {
+            if (!xpass_variant_ok<R>(v, G.nx) || xpass_scratch<R>(v, G.nx, 1) != 0) continue;
+            G.row_f = v;
+            const double ms = time_seq();
+            if (ms >= 0 && ms < best) { best = ms; keep = v; }
+        }
+        G.row_f = keep;
+        keep = G.col_f;
+        for (int v = 0; v < kNumColVariants; ++v) {
+            if (!colpass_variant_ok<R>(v, G.ny, G.nx) || colpass_scratch<R>(v, G.ny, 1) != 0) continue;
+            G.col_f = v;
+            const double ms = time_seq();
+            if (ms >= 0 && ms < best) { best = ms; keep = v; }
+        }
+        G.col_f = keep;
+    }
+    HIP_TRY(hipStreamSynchronize(b->st));
+    return SFO_OK;
 }
 
 template <typename R>
@@ -2201,6 +2285,14 @@ sfo_status sfo_destroy_batch(sfo_batch b)
     (void)hipStreamSynchronize(b->st);
     free_batch(b);
     return SFO_OK;
+}
+
+sfo_status sfo_batch_autotune(sfo_batch b, int32_t reps)
+{
+    AllocCount alloc_count;
+    if (!b) return fail(SFO_E_INVALID, "null batch");
+    if (reps < 1 || reps > 10000) return fail(SFO_E_INVALID, "reps must be in 1..10000");
+    return no_throw([&] { return b->c128 ? batch_tune<double>(b, reps) : batch_tune<float>(b, reps); });
 }
 
 sfo_status sfo_batch_set_graph(sfo_batch b, int32_t on)

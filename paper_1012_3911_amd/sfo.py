@@ -53,7 +53,8 @@ _lib = None
 EXPORTS = ["sfo_create_grid", "sfo_destroy_grid", "sfo_set_potential", "sfo_set_field",
            "sfo_set_vector_potential", "sfo_step", "sfo_propagate", "sfo_adjoint", "sfo_norm",
            "sfo_overlap", "sfo_fft", "sfo_create_batch", "sfo_destroy_batch", "sfo_propagate_batch",
-           "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_autotune", "sfo_get_plan",
+           "sfo_adjoint_batch", "sfo_batch_set_graph", "sfo_batch_check", "sfo_batch_autotune", "sfo_autotune",
+           "sfo_get_plan",
            "sfo_set_plan", "sfo_profile_enable", "sfo_profile_read", "sfo_time_pass", "sfo_autocorrelation",
            "sfo_spectrum", "sfo_set_vector_field", "sfo_eigenfunction", "sfo_adjoint_noalloc", "sfo_set_norm_watch", "sfo_adjoint_velocity", "sfo_last_error",
            "sfo_version"]
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "sfo_adjoint_batch": [P, P, P, I64, I64, P, P],
         "sfo_batch_set_graph": [P, I32],
         "sfo_batch_check": [P],
+        "sfo_batch_autotune": [P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -387,6 +389,9 @@ class Batch:
 
     def set_graph(self, on: bool):
         _check(_lib.sfo_batch_set_graph(self._h, 1 if on else 0), "sfo_batch_set_graph")
+
+    def autotune(self, reps: int = 10):
+        _check(_lib.sfo_batch_autotune(self._h, int(reps)), "sfo_batch_autotune")
 
     def propagate(self, psis, step0: int, nsteps: int):
         _check(_lib.sfo_propagate_batch(self._h, self._ptrs(psis, "psi"), int(step0), int(nsteps)),

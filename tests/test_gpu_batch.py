@@ -70,6 +70,48 @@ def test_batch_forward_matches_oracle(orc, dtype):
         assert err < FWD_TOL[dtype], (wl.n, err)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_autotune_matches_oracle(orc, dtype):
+    """sfo_batch_autotune picks the grouped forward launches' shapes on scratch
+    states: afterwards every problem still matches the oracle, the caller's
+    states are untouched by the tuning, and the reverse sweep (shapes
+    unchanged) equals the untuned batch's."""
+    import torch
+
+    from paper_1012_3911_amd import sfo
+
+    wls = mixed_problems()
+    step0, ns = 5, 30
+    grids = [make_grid(wl, dtype) for wl in wls]
+    psis = [to_device(wl.psi0, dtype) for wl in wls]
+    before = [p.clone() for p in psis]
+    b = sfo.Batch(grids)
+    b.autotune(2)
+    torch.cuda.synchronize()
+    for p, q in zip(psis, before):
+        assert torch.equal(p, q)
+    b.propagate(psis, step0, ns)
+    b.check()
+    torch.cuda.synchronize()
+    for wl, p in zip(wls, psis):
+        ref = oracle_run(orc, wl, nsteps=ns, step0=step0)
+        err = rel_l2(p.cpu().numpy(), ref)
+        print("tuned batch %-6s %-12s rel L2 %.2e" % (dtype, wl.n, err), flush=True)
+        assert err < FWD_TOL[dtype], (wl.n, err)
+    gs = [to_device(0.5 * wl.psi0, dtype) for wl in wls]
+    d1, _ = b.adjoint([p.clone() for p in psis], [g_.clone() for g_ in gs], step0, ns, want_dV0=False)
+    b.close()
+    b2 = sfo.Batch(grids)
+    d2, _ = b2.adjoint([p.clone() for p in psis], [g_.clone() for g_ in gs], step0, ns, want_dV0=False)
+    b2.check()
+    torch.cuda.synchronize()
+    for x, y in zip(d1, d2):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    b2.close()
+    for g in grids:
+        g.close()
+
+
 def test_batch_single_problem_and_zero_steps(orc):
     wls = mixed_problems()[3:4]
     got = run_batch(wls, "c128", 0, 0)
@@ -233,6 +275,7 @@ def test_control_batch_full_size(orc):
     psis = [to_device(wl.psi0, "c64") for wl in wls]
     n0 = [g.norm(p) for g, p in zip(grids, psis)]
     b = sfo.Batch(grids)
+    b.autotune(3)  # the grouped launches' shapes, as the benchmark runs them
     b.propagate(psis, 0, wls[0].nsteps)
     b.check()
     torch.cuda.synchronize()
@@ -266,8 +309,8 @@ def _overlap_grad(psiT, target, dv):
 def test_control_batch_full_size_gradient(orc):
     """Gradient of |<target|psi(T)>|^2 with respect to the 200 control amplitudes for
     every problem of the 64-problem control batch (complex64, 400 steps, one batched
-    forward call and one batched reverse sweep, grids autotuned as the benchmark runs
-    them).  Checked: the norm of every problem after the forward run (drift <= 1e-6);
+    forward call and one batched reverse sweep, grids and grouped launches autotuned
+    as the benchmark runs them).  Checked: the norm of every problem after the forward run (drift <= 1e-6);
     the largest 2-D problem against the complex128 single-grid adjoint and against
     central differences of the complex128 forward run at 4 amplitudes; one 8192-point
     line and one 256^2 problem against the oracle's stored-trajectory gradient
@@ -287,6 +330,7 @@ def test_control_batch_full_size_gradient(orc):
     psis = [to_device(wl.psi0, "c64") for wl in wls]
     n0 = [g.norm(p) for g, p in zip(grids, psis)]
     b = sfo.Batch(grids)
+    b.autotune(3)
     b.propagate(psis, 0, S)
     b.check()
     drifts = [g.norm(p) / a - 1 for g, p, a in zip(grids, psis, n0)]
