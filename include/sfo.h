@@ -305,14 +305,15 @@ sfo_status sfo_fft(sfo_grid g, void *psi_dev, int32_t sign);
  * replaying graphs.
  * sfo_batch_check: waits for the batch's stream; SFO_E_HIP if a launch
  * failed.
- * sfo_batch_autotune: chooses the tile shapes of the grouped forward
- * launches (a group's launch covers all its problems, so the shapes that
- * suit one grid need not suit the group) by timing `reps` steps of each 2-D
- * group's sequence in every row shape, then every column shape, on scratch
- * states it allocates and frees; the member grids' own plans and the
- * reverse sweep's shapes are unchanged, and results differ from those of
- * the member grids' shapes by rounding only.  Synchronises the stream;
- * reps in 1..10000, else SFO_E_INVALID. */
+ * sfo_batch_autotune: chooses the tile shapes of the grouped launches (a
+ * group's launch covers all its problems, so the shapes that suit one grid
+ * need not suit the group) by timing `reps` steps of each 2-D group's
+ * sequence, forward and in the reverse sweep, in every row shape, then
+ * every column shape, on scratch states it allocates and frees (it may grow
+ * the batch's partial-slot buffer); the member grids' own plans are
+ * unchanged, and results differ from those of the member grids' shapes by
+ * rounding only.  Synchronises the stream; reps in 1..10000, else
+ * SFO_E_INVALID. */
 sfo_status sfo_create_batch(const sfo_grid *grids, int32_t count, void *hip_stream, sfo_batch *out);
 sfo_status sfo_destroy_batch(sfo_batch b);
 sfo_status sfo_propagate_batch(sfo_batch b, void *const *psi_devs, int64_t step0, int64_t nsteps);

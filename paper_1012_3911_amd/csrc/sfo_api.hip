@@ -1428,9 +1428,9 @@ struct sfo_batch_s {
         int ndim, nx, ny;
         int off, count;  // ids[off .. off+count)
         sfo_grid rep;    // a grid of the group: its tables and tile shapes serve all
-        // the forward passes' shapes chosen for the grouped launches
-        // (sfo_batch_autotune); -1: those of rep
-        int row_f = -1, col_f = -1;
+        // the shapes chosen for the grouped launches of the forward runs and
+        // of the reverse sweep (sfo_batch_autotune); -1: those of rep
+        int row_f = -1, col_f = -1, row2_f = -1, col2_f = -1;
     };
     std::vector<Group> groups;
     std::vector<int> ids;
@@ -1491,6 +1491,18 @@ void group_batch(sfo_batch b, const sfo_grid *grids, int count)
 
 // Descriptors of every problem for one call; *work_need: the moment and
 // partial workspace of a reverse sweep (doubles).
+// Shapes of a 2-D group's grouped launches with ns states.
+int group_row(const sfo_batch_s::Group &G, int ns)
+{
+    const int f = ns == 1 ? G.row_f : G.row2_f;
+    return f >= 0 ? f : row_shape(G.rep, ns);
+}
+int group_col(const sfo_batch_s::Group &G, int ns)
+{
+    const int f = ns == 1 ? G.col_f : G.col2_f;
+    return f >= 0 ? f : col_shape(G.rep, 1, ns);
+}
+
 template <typename R>
 std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void *const *gadj, double *const *dE,
                                       double *const *dV, int64_t nsteps, int64_t *work_need)
@@ -1523,7 +1535,7 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
         if (g->ndim == 2) {
             for (const auto &G : b->groups)
                 if (G.ndim == 2 && G.nx == q.nx && G.ny == q.ny)
-                    q.gslots = std::max(1, xpass_groups<R>(row_shape(G.rep, 2), q.nx, q.ny));
+                    q.gslots = std::max(1, xpass_groups<R>(group_row(G, 2), q.nx, q.ny));
         }
         if (gadj) {
             q.gadj = (cx<R> *)gadj[i];
@@ -1540,10 +1552,6 @@ std::vector<BatchProb<R>> batch_probs(const sfo_batch b, void *const *psi, void 
 // The tile shapes of every 2-D group's passes: a captured graph holds launches
 // of these shapes (grid sizes, and in the reverse sweep the partial-slot
 // stride of the row pass), so it is valid only while they are unchanged.
-// Shapes of a 2-D group's grouped launches with ns states.
-int group_row(const sfo_batch_s::Group &G, int ns) { return ns == 1 && G.row_f >= 0 ? G.row_f : row_shape(G.rep, ns); }
-int group_col(const sfo_batch_s::Group &G, int ns) { return ns == 1 && G.col_f >= 0 ? G.col_f : col_shape(G.rep, 1, ns); }
-
 std::vector<int> batch_shapes(const sfo_batch b)
 {
     std::vector<int> v;
@@ -1571,7 +1579,7 @@ hipError_t batch_enqueue(sfo_batch b, int dir, int64_t step0, int64_t nsteps, hi
         const BatchProb<R> *ph = (const BatchProb<R> *)b->probs_h.data();
         for (const auto &G : b->groups) {
             if (G.ndim != 2) continue;
-            const int launched = std::max(1, xpass_groups<R>(row_shape(G.rep, 2), G.nx, G.ny));
+            const int launched = std::max(1, xpass_groups<R>(group_row(G, 2), G.nx, G.ny));
             for (int k = 0; k < G.count; ++k)
                 if (b->probs_h.size() < sizeof(BatchProb<R>) * b->grids.size() || ph[b->ids[G.off + k]].gslots != launched)
                     return hipErrorInvalidValue;
@@ -1734,6 +1742,74 @@ template <typename R> sfo_status batch_tune(sfo_batch b, int reps)
             if (ms >= 0 && ms < best) { best = ms; keep = v; }
         }
         G.col_f = keep;
+    }
+    // the reverse sweep's two-state launches: scratch adjoint states; the
+    // partial slots follow the row shape being timed (descriptors rebuilt)
+    TimingScratch ga;
+    HIP_TRY(dev_malloc(&ga.mem, sizeof(cx<R>) * total));
+    HIP_TRY(hipMemsetAsync(ga.mem, 0, sizeof(cx<R>) * total, b->st));
+    std::vector<void *> gptr((size_t)n);
+    off = 0;
+    for (int i = 0; i < n; ++i) {
+        gptr[(size_t)i] = (cx<R> *)ga.mem + off;
+        off += (size_t)b->grids[(size_t)i]->ntot;
+    }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        sfo_batch_s::Group &G = b->groups[gi];
+        if (G.ndim != 2) continue;
+        int64_t steps = reps;
+        for (int k = 0; k < G.count; ++k) {
+            const sfo_grid g = b->grids[(size_t)b->ids[(size_t)(G.off + k)]];
+            if (g->ebar_steps > 0) steps = std::min<int64_t>(steps, g->ebar_steps);
+        }
+        sfo_status err = SFO_OK;
+        auto time_rev = [&]() {
+            int64_t wneed = 0;
+            (void)batch_probs<R>(b, ptr.data(), gptr.data(), nullptr, nullptr, steps, &wneed);
+            if (hipStreamSynchronize(b->st) != hipSuccess) return -1.0;
+            if (wneed > b->work_cap) {
+                (void)hipFree(b->work);
+                b->work = nullptr;
+                b->work_cap = 0;
+                if (dev_malloc(&b->work, sizeof(double) * wneed) != hipSuccess) {
+                    err = fail(SFO_E_NOMEM, "batch autotune: device allocation failed");
+                    return -1.0;
+                }
+                b->work_cap = wneed;
+            }
+            const std::vector<BatchProb<R>> Q = batch_probs<R>(b, ptr.data(), gptr.data(), nullptr, nullptr, steps, &wneed);
+            const size_t qb = sizeof(BatchProb<R>) * Q.size();
+            if (hipMemcpy(b->probs_d, Q.data(), qb, hipMemcpyHostToDevice) != hipSuccess) return -1.0;
+            b->probs_h.assign((const char *)Q.data(), (const char *)Q.data() + qb);
+            double best = -1.0;
+            for (int trial = 0; trial < 3; ++trial) {
+                const double ms = time_launches_on(b->st, ts.a, ts.b, 1, [&] {
+                    return batch_enqueue<R>(b, -1, 0, steps, b->st, nullptr, (int)gi);
+                });
+                if (ms >= 0 && (best < 0 || ms < best)) best = ms;
+            }
+            return best;
+        };
+        G.row2_f = row_shape(G.rep, 2);
+        G.col2_f = col_shape(G.rep, 1, 2);
+        double best = time_rev();
+        int keep = G.row2_f;
+        for (int v = 0; v < kNumRowVariants && !err; ++v) {
+            if (!xpass_variant_ok<R>(v, G.nx) || xpass_scratch<R>(v, G.nx, 2) != 0) continue;
+            G.row2_f = v;
+            const double ms = time_rev();
+            if (ms >= 0 && ms < best) { best = ms; keep = v; }
+        }
+        G.row2_f = keep;
+        keep = G.col2_f;
+        for (int v = 0; v < kNumColVariants && !err; ++v) {
+            if (!colpass_variant_ok<R>(v, G.ny, G.nx, 2) || colpass_scratch<R>(v, G.ny, 2) != 0) continue;
+            G.col2_f = v;
+            const double ms = time_rev();
+            if (ms >= 0 && ms < best) { best = ms; keep = v; }
+        }
+        G.col2_f = keep;
+        if (err) return err;
     }
     HIP_TRY(hipStreamSynchronize(b->st));
     return SFO_OK;

@@ -72,10 +72,10 @@ def test_batch_forward_matches_oracle(orc, dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_batch_autotune_matches_oracle(orc, dtype):
-    """sfo_batch_autotune picks the grouped forward launches' shapes on scratch
-    states: afterwards every problem still matches the oracle, the caller's
-    states are untouched by the tuning, and the reverse sweep (shapes
-    unchanged) equals the untuned batch's."""
+    """sfo_batch_autotune picks the grouped launches' shapes (forward runs and
+    reverse sweep) on scratch states: the caller's states are untouched by the
+    tuning, every problem still matches the oracle forward, and the tuned
+    reverse sweep's gradients equal the untuned batch's to rounding."""
     import torch
 
     from paper_1012_3911_amd import sfo
@@ -105,8 +105,10 @@ def test_batch_autotune_matches_oracle(orc, dtype):
     d2, _ = b2.adjoint([p.clone() for p in psis], [g_.clone() for g_ in gs], step0, ns, want_dV0=False)
     b2.check()
     torch.cuda.synchronize()
+    tol = 1e-12 if dtype == "c128" else 1e-5
     for x, y in zip(d1, d2):
-        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.linalg.norm(x - y) <= tol * np.linalg.norm(y)
     b2.close()
     for g in grids:
         g.close()
