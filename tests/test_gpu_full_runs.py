@@ -2,6 +2,9 @@
 workloads, at their full sizes, in the launch configuration the benchmark
 times (autotuned tile shapes).
 
+The 4096^2 grid (the largest square grid, which the benchmark times beside
+the 2-D workload) runs a 100-step pulse of the same workload.
+
 Each workload is advanced in chunks; the oracle state, the complex128 GPU
 state and the complex64 GPU state are carried from chunk to chunk (module
 cache), so every checkpoint compares all three after the same number of
@@ -109,6 +112,16 @@ def test_2d_softcore_laser_2048sq_500_steps(orc, step):
     r = _run(orc, "2d", W.softcore_2d_laser)
     r.advance_to(step)
     r.check("2d 2048^2")
+
+
+@pytest.mark.parametrize("step", [50, 100])
+def test_2d_softcore_laser_4096sq_100_steps(orc, step):
+    """4096^2 soft-core atom with the dipole laser term (the largest square grid:
+    256 MiB of complex128 state, the tile shapes that stream from HBM), tau = 0.02,
+    a 100-step pulse."""
+    r = _run(orc, "2d4096", lambda: W.softcore_2d_laser(n=4096, nsteps=100))
+    r.advance_to(step)
+    r.check("2d 4096^2")
 
 
 @pytest.mark.parametrize("step", [50, 100, 150, 200])
