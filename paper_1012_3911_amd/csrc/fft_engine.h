@@ -415,9 +415,10 @@ __device__ __forceinline__ void tw_base_load(TwBase<N, RAD> &w, const TwEntry<fl
     using Sh = LineShape<N, RAD>;
     if constexpr (S < Sh::NST) {
         static_assert(Sh::RV / Sh::radix(S) == 1, "one butterfly per thread in a twiddled stage");
-        constexpr int L = Sh::span(S);
-        twiddle_base(tw, Sh::tw_offset(S), (uint32_t)(t & (L - 1)) * (uint32_t)sizeof(TwEntry<float>), w.r[S - 1],
-                     w.i[S - 1]);
+        // both evaluated here at compile time (as call arguments the recursive
+        // constexpr functions can end up as run-time calls with a stack frame)
+        constexpr int L = Sh::span(S), TWO = Sh::tw_offset(S);
+        twiddle_base(tw, TWO, (uint32_t)(t & (L - 1)) * (uint32_t)sizeof(TwEntry<float>), w.r[S - 1], w.i[S - 1]);
         tw_base_load<N, RAD, S + 1>(w, tw, t);
     }
 }
@@ -428,8 +429,8 @@ __device__ __forceinline__ void tw_base_load(TwBase<N, RAD> &w, const TwEntry<do
     using Sh = LineShape<N, RAD>;
     if constexpr (S < Sh::NST) {
         static_assert(Sh::RV / Sh::radix(S) == 1, "one butterfly per thread in a twiddled stage");
-        constexpr int L = Sh::span(S);
-        const TwEntry<double> e = tw[Sh::tw_offset(S) + (t & (L - 1))];
+        constexpr int L = Sh::span(S), TWO = Sh::tw_offset(S);  // compile time (see above)
+        const TwEntry<double> e = tw[TWO + (t & (L - 1))];
         w.r[S - 1] = e.r;
         w.i[S - 1] = e.i;
         tw_base_load<N, RAD, S + 1>(w, tw, t);
