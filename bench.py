@@ -54,35 +54,35 @@ TRAFFIC_SOURCES = ["fft_engine.h", "pass_kernels.h"]
 TRAFFIC_TABLE = ("sfo_impl.h", b"struct RowVariant {", b"constexpr int kNumColVariants")
 _KIB = 1024
 MEASURED_TRAFFIC = {
-    "sources_sha256": "0b87eae5a4c0b307fd7839139852cd83e3d0d9fc18ec71f1f697a5788461d4f0",
+    "sources_sha256": "1284db5b488a12aa1ab452bbee0d52b4194078c930b7c3b07c609f47e6fb5bd4",
     # pass/shape: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch as read; the pipelined
     # column shapes that differ only in groups per work-group share one kernel and one entry;
     # shapes whose kernel spills registers (never tuned in) have none
     "c64": {
-        "row/0": (24726, 32768), "row/1": (24726, 32768), "row/2": (24720, 32768), "row/3": (24725, 32768),
-        "row/4": (24724, 32768), "row/5": (24702, 32768), "row/6": (24696, 32768), "row/7": (24700, 32768),
-        "row/8": (24692, 32768), "row/9": (24689, 32768), "row/10": (24721, 32768), "row/11": (24725, 32768),
-        "row/12": (24721, 32768), "row/13": (24698, 32768), "row/14": (24726, 32768), "row/15": (24725, 32768),
-        "row/16": (24721, 32768), "row/17": (24698, 32768), "row/18": (24738, 32768), "row/19": (24738, 32768),
-        "column/0": (16658, 32811), "column/1": (16658, 32776), "column/2": (16658, 33254),
-        "column/4": (16658, 32776), "column/5": (16660, 33203), "column/7": (16769, 32792),
-        "column/8": (16627, 34003), "column/9": (16809, 32768), "column/10": (16818, 32768),
-        "column/11": (16809, 32768), "column/12": (16818, 32768), "column/13": (16841, 32768),
-        "column/14": (16856, 32768), "column/15": (16841, 32768), "column/16": (16856, 32768),
-        "column/17": (16662, 33343), "column/18": (16654, 33000), "column/19": (16657, 33031),
-        "column/20": (16655, 33444), "column/21": (16659, 33568), "column/22": (16866, 32770),
+        "row/0": (24726, 32768), "row/1": (24724, 32768), "row/2": (24718, 32768), "row/3": (24726, 32768),
+        "row/4": (24722, 32768), "row/5": (24698, 32768), "row/6": (24698, 32768), "row/7": (24702, 32768),
+        "row/8": (24691, 32768), "row/9": (24688, 32768), "row/10": (24720, 32768), "row/11": (24723, 32768),
+        "row/12": (24720, 32768), "row/13": (24702, 32768), "row/14": (24726, 32768), "row/15": (24723, 32768),
+        "row/16": (24720, 32768), "row/17": (24702, 32768), "row/18": (24735, 32768), "row/19": (24746, 32768),
+        "column/0": (16657, 32798), "column/1": (16658, 32776), "column/2": (16658, 33258),
+        "column/4": (16658, 32776), "column/5": (16660, 33191), "column/7": (16768, 32810),
+        "column/8": (16626, 36052), "column/9": (16808, 32769), "column/10": (16816, 32768),
+        "column/11": (16808, 32769), "column/12": (16816, 32768), "column/13": (16840, 32768),
+        "column/14": (16856, 32768), "column/15": (16840, 32768), "column/16": (16856, 32768),
+        "column/17": (16660, 33378), "column/18": (16654, 33006), "column/19": (16657, 33040),
+        "column/20": (16655, 33428), "column/21": (16659, 33596), "column/22": (16866, 32769),
     },
     "c128": {
-        "row/0": (49611, 65536), "row/1": (49429, 65536), "row/2": (49556, 65536), "row/3": (49620, 65536),
-        "row/4": (49633, 65536), "row/5": (49391, 65536), "row/6": (49460, 65536), "row/7": (49393, 65536),
-        "row/8": (49384, 65536), "row/9": (49470, 65536), "row/10": (49616, 65536), "row/11": (49435, 65536),
-        "row/12": (49618, 65536), "row/13": (49390, 65536), "row/14": (49331, 65536), "row/15": (49321, 65536),
-        "row/16": (49332, 65536), "row/18": (49332, 65536), "row/19": (49342, 65536), "column/1": (33465, 76733),
-        "column/2": (34034, 91397), "column/4": (33459, 77377), "column/5": (33894, 90334),
-        "column/7": (33373, 65732), "column/8": (33384, 87955), "column/10": (33365, 67914),
-        "column/12": (33365, 67914), "column/14": (33436, 65791), "column/16": (33436, 65791),
-        "column/18": (33187, 65737), "column/19": (33187, 66158), "column/20": (33305, 78777),
-        "column/21": (35648, 82372), "column/22": (33285, 68215),
+        "row/0": (49616, 65536), "row/1": (49432, 65536), "row/2": (49558, 65536), "row/3": (49598, 65536),
+        "row/4": (49613, 65536), "row/5": (49384, 65536), "row/6": (49464, 65536), "row/7": (49388, 65536),
+        "row/8": (49376, 65536), "row/9": (49449, 65536), "row/10": (49627, 65536), "row/11": (49435, 65536),
+        "row/12": (49585, 65536), "row/13": (49394, 65536), "row/14": (49328, 65536), "row/15": (49322, 65536),
+        "row/16": (49332, 65536), "row/17": (49288, 65536), "row/18": (49340, 65536), "row/19": (49342, 65536),
+        "column/1": (33466, 76738), "column/2": (34058, 91756), "column/4": (33462, 77112),
+        "column/5": (33910, 89643), "column/7": (33373, 65765), "column/8": (33382, 87118),
+        "column/10": (33367, 69558), "column/12": (33367, 69558), "column/14": (33433, 65779),
+        "column/16": (33433, 65779), "column/18": (33185, 65709), "column/19": (33185, 66244),
+        "column/20": (33300, 79756), "column/21": (35456, 83055), "column/22": (33282, 69437),
     },
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0  # plain-copy calibration of the two counters
